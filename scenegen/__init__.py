@@ -1,0 +1,187 @@
+"""Seeded synthetic multichannel SAR scenes with Kronecker clutter.
+
+This module only draws random numbers in the shapes the detector consumes; it
+holds none of the detector's arithmetic (no covariance estimation, no
+Kronecker fitting, no projection, no statistic).  Both the FP64 oracle tests
+and the GPU path read the frames it writes, so the two sides see the same
+bytes.
+
+Model (Sec. 2, SIRV clutter model; Eqs. (4)-(9) of the paper):
+  * one snapshot per pixel is a p x q complex array X (p channels, q azimuth
+    samples); its vector form is x = vec(X^T), i.e. x[i*q + j] = X[i, j]
+    (channel-major), which is the ordering under which the clutter covariance
+    is A (x) B with a p x p space factor A and a q x q time factor B;
+  * clutter + noise of each pixel is an independent draw from
+    CN(0, A (x) B + sigma^2 I) with sigma^2 = 1 and texture tau = 1;
+  * A has rank r_a (rank 1 is the calibration-error model of Eq. (9)), B has
+    rank r_b; their nonzero eigenvalues are drawn from U[0.5, 1], their
+    eigenvectors are the Q factor of a complex Gaussian matrix, and B is scaled
+    so that tr(A (x) B)/(p q) equals the clutter-to-noise ratio (per element);
+  * optionally the factors rotate slowly over the scene: within block
+    (bx, by) of `block` x `block` pixels the eigenvector bases are
+    expm(j*kappa*(bx*G1 + by*G2)) @ U0 with G1, G2 random Hermitian matrices of
+    unit spectral norm (one pair for A, one for B);
+  * moving targets follow Eq. (8): x_t = alpha * a(theta) (x) b_s with the
+    spatial steering a_i = exp(j*i*theta), theta ~ U[0, 2 pi), the temporal
+    factor equal to the detector's temporal steering b_s (default all-ones),
+    and |alpha|^2 = 10^(SNR/10) per element.
+
+Layout of the returned frame: complex64 array x[p][H][W][q] (q fastest): one
+H x (W*q) image per channel, pixel (r, c) owning the q consecutive samples
+x[i, r, c, :] of channel i.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional, Sequence, Tuple, Union
+
+import numpy as np
+
+BASE_SEED = 16040362
+
+
+@dataclasses.dataclass(frozen=True)
+class SceneSpec:
+    p: int
+    q: int
+    H: int
+    W: int
+    r_a: int = 1
+    r_b: int = 3
+    cnr_db: float = 30.0
+    snr_db: Union[float, Tuple[float, float]] = 10.0
+    n_targets: int = 5
+    block: Optional[int] = None      # factor rotation block size (pixels); None = one factor pair
+    kappa: float = 0.2               # rotation per block (radians)
+    b_steer: Optional[Tuple[complex, ...]] = None   # temporal steering of targets; None = ones
+
+
+# Workload shapes of the paper's single-pass Kron-STAP (Sec. 6.3) at the sizes
+# this library is measured on.  Tiny frame: oracle-checkable in seconds.
+TINY = SceneSpec(p=3, q=8, H=64, W=64, r_a=1, r_b=3, n_targets=5, snr_db=10.0)
+# Full frame, plain FP32 path: 2048^2 pixels, p=3, q=16, slowly rotating factors.
+FULL_FRAME = SceneSpec(p=3, q=16, H=2048, W=2048, r_a=1, r_b=4, n_targets=200,
+                       snr_db=(0.0, 15.0), block=256)
+# Mixed-precision workload: p=5, q=24, 1024^2 pixels.
+MIXED = SceneSpec(p=5, q=24, H=1024, W=1024, r_a=1, r_b=4, n_targets=200,
+                  snr_db=(0.0, 15.0), block=256)
+
+
+def _unitary_q(rng: np.random.Generator, n: int, r: int) -> np.ndarray:
+    g = (rng.standard_normal((n, r)) + 1j * rng.standard_normal((n, r))) / np.sqrt(2.0)
+    qm, _ = np.linalg.qr(g)
+    return qm[:, :r]
+
+
+def _hermitian_unit(rng: np.random.Generator, n: int) -> np.ndarray:
+    g = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) / np.sqrt(2.0)
+    h = (g + g.conj().T) / 2.0
+    return h / np.max(np.abs(np.linalg.eigvalsh(h)))
+
+
+def _expm_i_herm(h: np.ndarray, t: float) -> np.ndarray:
+    """expm(j*t*h) for Hermitian h, via its eigendecomposition."""
+    lam, v = np.linalg.eigh(h)
+    return (v * np.exp(1j * t * lam)) @ v.conj().T
+
+
+@dataclasses.dataclass
+class Scene:
+    spec: SceneSpec
+    seed: int
+    x: np.ndarray                    # complex64 [p][H][W][q]
+    targets: np.ndarray              # int64 [n_targets, 2] (row, col)
+    target_snr_db: np.ndarray        # float64 [n_targets]
+    factors: list                    # per block: (A, B) complex128
+
+
+def _factor_pairs(spec: SceneSpec, rng: np.random.Generator):
+    p, q = spec.p, spec.q
+    ua0 = _unitary_q(rng, p, spec.r_a)
+    ub0 = _unitary_q(rng, q, spec.r_b)
+    la = rng.uniform(0.5, 1.0, spec.r_a)
+    lb = rng.uniform(0.5, 1.0, spec.r_b)
+    scale = 10.0 ** (spec.cnr_db / 10.0) * p * q / (la.sum() * lb.sum())
+    lb = lb * scale
+    if spec.block is None:
+        nby = nbx = 1
+        blk = max(spec.H, spec.W)
+    else:
+        blk = spec.block
+        nby = -(-spec.H // blk)
+        nbx = -(-spec.W // blk)
+    ga1, ga2 = _hermitian_unit(rng, p), _hermitian_unit(rng, p)
+    gb1, gb2 = _hermitian_unit(rng, q), _hermitian_unit(rng, q)
+    pairs = {}
+    for by in range(nby):
+        for bx in range(nbx):
+            if spec.block is None:
+                ua, ub = ua0, ub0
+            else:
+                ua = _expm_i_herm(bx * ga1 + by * ga2, spec.kappa) @ ua0
+                ub = _expm_i_herm(bx * gb1 + by * gb2, spec.kappa) @ ub0
+            a = (ua * la) @ ua.conj().T
+            b = (ub * lb) @ ub.conj().T
+            pairs[(by, bx)] = (a, b)
+    return pairs, blk, nby, nbx
+
+
+def make_scene(spec: SceneSpec, seed: int = BASE_SEED) -> Scene:
+    """Draw one frame.  Deterministic in (spec, seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p, q, H, W = spec.p, spec.q, spec.H, spec.W
+    pq = p * q
+    pairs, blk, nby, nbx = _factor_pairs(spec, rng)
+    x = np.empty((p, H, W, q), dtype=np.complex64)
+    factors = []
+    for by in range(nby):
+        for bx in range(nbx):
+            a, b = pairs[(by, bx)]
+            factors.append((a, b))
+            cov = np.kron(a, b) + np.eye(pq)
+            lam, v = np.linalg.eigh(cov)
+            root = (v * np.sqrt(np.clip(lam, 0.0, None))) @ v.conj().T   # Hermitian square root
+            r0, r1 = by * blk, min(H, (by + 1) * blk)
+            c0, c1 = bx * blk, min(W, (bx + 1) * blk)
+            npx = (r1 - r0) * (c1 - c0)
+            w = np.empty((npx, pq), dtype=np.complex64)
+            w.real = rng.standard_normal((npx, pq), dtype=np.float32)
+            w.imag = rng.standard_normal((npx, pq), dtype=np.float32)
+            w *= np.float32(1.0 / np.sqrt(2.0))
+            snap = w @ root.T.astype(np.complex64)          # rows: root @ w_i
+            snap = snap.reshape(r1 - r0, c1 - c0, p, q)
+            x[:, r0:r1, c0:c1, :] = snap.transpose(2, 0, 1, 3)
+    # moving targets, Eq. (8)
+    nt = spec.n_targets
+    rows = rng.integers(0, H, nt)
+    cols = rng.integers(0, W, nt)
+    if isinstance(spec.snr_db, tuple):
+        snr = rng.uniform(spec.snr_db[0], spec.snr_db[1], nt)
+    else:
+        snr = np.full(nt, float(spec.snr_db))
+    theta = rng.uniform(0.0, 2.0 * np.pi, nt)
+    phase = rng.uniform(0.0, 2.0 * np.pi, nt)
+    bs = np.ones(q, dtype=np.complex128) if spec.b_steer is None else np.asarray(spec.b_steer, np.complex128)
+    for t in range(nt):
+        alpha = np.sqrt(10.0 ** (snr[t] / 10.0)) * np.exp(1j * phase[t])
+        av = np.exp(1j * theta[t] * np.arange(p))
+        x[:, rows[t], cols[t], :] += (alpha * np.outer(av, bs)).astype(np.complex64)
+    return Scene(spec=spec, seed=seed, x=x, targets=np.stack([rows, cols], 1),
+                 target_snr_db=snr, factors=factors)
+
+
+def random_pixels(H: int, W: int, count: int, seed: int,
+                  region: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Seeded (row, col) sample of pixels, int32 [count, 2], inside
+    region = (r0, r1, c0, c1) (half-open) if given."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r0, r1, c0, c1 = (0, H, 0, W) if region is None else region
+    rr = rng.integers(r0, r1, count)
+    cc = rng.integers(c0, c1, count)
+    return np.stack([rr, cc], 1).astype(np.int32)
+
+
+def white_noise(shape, seed: int) -> np.ndarray:
+    """Seeded CN(0, 1) samples, complex128."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
