@@ -1,0 +1,184 @@
+/*
+ * kstap.h - C ABI of the per-pixel Kronecker STAP library for AMD MI355X (gfx950).
+ *
+ * The library implements, for every pixel of a multichannel SAR frame, the
+ * Kron-STAP clutter-cancellation pass of Greenewald, Zelnio & Hero,
+ * "Kronecker STAP and SAR GMTI" (SPIE 2016):
+ *   - the sample covariance S of the pixel's n training snapshots
+ *     (Sec. 1.1, Eq. (2)), with the snapshot vector x = vec(X^T) of Sec. 2;
+ *   - the low-rank Kronecker fit S ~ A (x) B by LR-Kron (Sec. 4, Algorithm 2,
+ *     on the rearrangement of Algorithm 1), rank(A) <= r_a, and B truncated
+ *     to rank r_b once at the end (Sec. 4, relaxation after Eq. (17));
+ *   - the Kron-STAP projector F = (I - U_A U_A^H) (x) (I - U_B U_B^H)
+ *     (Sec. 5, Eq. (25)) used as the filter w = F d (Eq. (23));
+ *   - the normalised output statistic T = max_h |d^H F x|^2 / (d^H F d) over
+ *     spatial steerings h with d = h (x) b_s (Sec. 6.3, Eq. (26)), which
+ *     equals ||F_A X conj(F_B b_s)||^2 / (b_s^H F_B b_s); and D = (T > tau).
+ *
+ * Conventions shared by every entry point
+ *   - Frames are complex64 (interleaved re, im float pairs) in DEVICE memory,
+ *     laid out x[p][H][W][q] (q fastest): channel i, pixel (r, c) owns the q
+ *     consecutive azimuth samples x[i][r][c][0..q-1].
+ *   - Pixel (r, c) is processed iff every training offset (r+dr, c+dc) of the
+ *     stencil lies inside the frame (its "valid region"); elsewhere T = 0 and
+ *     D = 0.
+ *   - Every call returns a stap_status.  Nothing throws, aborts or exits
+ *     across the ABI.  On error, stap_last_error() returns a message
+ *     (thread-local, valid until the next call on the same thread).
+ *   - Argument checks happen on the host before anything is enqueued.  Calls
+ *     that take a `hip_stream` (a hipStream_t, NULL = the default stream) only
+ *     enqueue work and return; errors that happen on the device surface at the
+ *     caller's next synchronisation.
+ *   - Non-finite input samples give T = NaN and D = 0 for the affected pixels;
+ *     that is not an error.  An all-zero training set gives T = 0.
+ *   - The caller owns every buffer passed in and keeps it alive until the
+ *     enqueued work has completed.
+ */
+#ifndef KSTAP_H_
+#define KSTAP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  STAP_OK = 0,
+  STAP_ERR_INVALID_ARG = 1,   /* a pointer, size or configuration value is out of range */
+  STAP_ERR_UNSUPPORTED = 2,   /* valid, but no kernel is built for this (p, q, precision) */
+  STAP_ERR_OUT_OF_MEMORY = 3, /* a host or device allocation failed */
+  STAP_ERR_DEVICE = 4,        /* the HIP runtime reported an error */
+  STAP_ERR_BUSY = 5,          /* admission refused (serving): retry later */
+  STAP_ERR_INTERNAL = 6
+} stap_status;
+
+typedef enum {
+  STAP_PREC_FP32 = 0,   /* covariance on FP32 MFMA, everything else FP32 (eta terms FP64) */
+  STAP_PREC_BF16X3 = 1  /* covariance as three BF16 MFMA products (hi*hi + hi*lo + lo*hi) with
+                           FP32 accumulation; eigensolves and normalisation in FP64 */
+} stap_precision;
+
+typedef enum {
+  STAP_STAT_GLRT = 0,   /* T maximised over the spatial steering h (Sec. 6.3) */
+  STAP_STAT_FIXED = 1   /* T for the single spatial steering h_steer */
+} stap_stat_mode;
+
+/* Detector configuration.  Fill with stap_config_default(), then override. */
+typedef struct {
+  int32_t p;              /* channels, 1 <= p <= 8 */
+  int32_t q;              /* azimuth samples per pixel, 2 <= q <= 32, p*q <= 128 */
+  int32_t n;              /* training snapshots per pixel, 1 <= n <= 256 */
+  const int32_t* stencil; /* host, n (dr, dc) pairs, |dr|,|dc| <= 64, no (0,0), no repeats;
+                             NULL = default stencil (below).  Copied by stap_plan_create. */
+  int32_t window;         /* default stencil: square window side W (even); 0 = smallest even
+                             W >= 10 with W*W - guard*guard >= n */
+  int32_t guard;          /* default stencil: odd side of the excluded centre block (3) */
+  int32_t r_a;            /* rank of the space factor, 1 <= r_a <= min(p, 4) */
+  int32_t r_b;            /* rank of the time factor, 0 <= r_b <= min(q, 8); 0 means F_B = I */
+  double eps;             /* LR-Kron stop: |eta_k - eta_{k-1}| <= eps; <= 0: run max_iter */
+  int32_t min_iter;       /* >= 1 */
+  int32_t max_iter;       /* >= min_iter, <= 1000 */
+  int32_t stat_mode;      /* stap_stat_mode */
+  const float* b_steer;   /* host, q complex (re, im pairs) temporal steering; NULL = all ones */
+  const float* h_steer;   /* host, p complex spatial steering; required for STAP_STAT_FIXED */
+  double tau;             /* > 0: threshold used as given; else from pfa */
+  double pfa;             /* tau = upper-tail pfa quantile of Gamma(p - r_a, 1), the null law
+                             of T under white noise; 0 < pfa < 1 */
+  int32_t precision;      /* stap_precision */
+} stap_config;
+
+/* Default stencil: offsets (dr, dc) of the window [-W/2, W/2-1]^2 minus the
+ * centred guard x guard block, ordered by (dr^2 + dc^2, dr, dc); the first n
+ * are used.  (The paper trains on "representative range bins", Sec. 1.1; the
+ * window rule is this library's choice.) */
+
+typedef struct stap_plan_s stap_plan_t;
+
+/* Fills *cfg with defaults: p=3, q=16, n=200, stencil=NULL, window=0,
+ * guard=3, r_a=1, r_b=4, eps=1e-6, min_iter=2, max_iter=50, GLRT, b_steer=NULL,
+ * h_steer=NULL, tau=0, pfa=1e-4, FP32.  Errors: INVALID_ARG if cfg is NULL. */
+stap_status stap_config_default(stap_config* cfg);
+
+/* Validates *cfg, builds the stencil, computes tau, and copies every host
+ * array.  Host only: no device memory is allocated and nothing is launched,
+ * so a plan may be used on any device and from several streams at once.
+ * Errors: INVALID_ARG (bad value), UNSUPPORTED (no kernel for p, q, precision),
+ * OUT_OF_MEMORY. */
+stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out);
+
+/* Frees a plan (NULL is accepted).  The plan must not be in use by work that
+ * is still enqueued. */
+stap_status stap_plan_destroy(stap_plan_t* plan);
+
+/* Plan facts: threshold tau, window side, and the stencil extent
+ * (min/max dr, min/max dc).  Any output pointer may be NULL. */
+stap_status stap_plan_info(const stap_plan_t* plan, double* tau, int32_t* window,
+                           int32_t* dr_min, int32_t* dr_max, int32_t* dc_min, int32_t* dc_max);
+
+/* Copies the plan's stencil (n (dr, dc) pairs) into host memory `out`
+ * (2*n int32).  Errors: INVALID_ARG. */
+stap_status stap_plan_stencil(const stap_plan_t* plan, int32_t* out);
+
+/* Half-open valid region [r0, r1) x [c0, c1) of an H x W frame; empty
+ * (r0 == r1 or c0 == c1) if the stencil does not fit.  Errors: INVALID_ARG. */
+stap_status stap_valid_region(const stap_plan_t* plan, int32_t H, int32_t W,
+                              int32_t* r0, int32_t* r1, int32_t* c0, int32_t* c1);
+
+/* Whole-frame pass.  x: device complex64 [p][H][W][q]; T: device float [H][W];
+ * D: device uint8 [H][W] or NULL.  Every element of T (and D) is written.
+ * 1 <= H, W and p*H*W*q < 2^31.  Enqueued on hip_stream (hipStream_t).
+ * Errors: INVALID_ARG, UNSUPPORTED, DEVICE (launch failed). */
+stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t W,
+                     float* T, uint8_t* D, void* hip_stream);
+
+/* Per-pixel probe: the same computation for a list of pixels, with the
+ * intermediate results.  All pointers are device memory:
+ *   pix   int32 [npix][2] (r, c)   (pixels outside the valid region get T = 0,
+ *                                   eta = 0, iters = 0, zero bases)
+ *   UA    complex64 [npix][p][r_a]  orthonormal basis of the space subspace
+ *   UB    complex64 [npix][q][r_b]  orthonormal basis of the time subspace
+ *   eta   float [npix]              last LR-Kron relative residual
+ *   iters int32 [npix]              LR-Kron iterations run
+ *   T     float [npix]
+ * Any of UA, UB, eta, iters may be NULL.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
+typedef struct {
+  float* UA;
+  float* UB;
+  float* eta;
+  int32_t* iters;
+  float* T;
+} stap_probe_out;
+
+stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_t W,
+                       const int32_t* pix, int32_t npix, const stap_probe_out* out,
+                       void* hip_stream);
+
+/* Batched uneven tiles: runs every tile (each with its own plan, frame, size
+ * and outputs) in one persistent launch ordered longest-first.  Results are
+ * identical to stap_run on each tile alone.  `tiles` is a host array.  The
+ * call copies the tile table to the device and waits for that copy before
+ * returning; the compute itself is only enqueued.
+ * Errors: INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
+typedef struct {
+  const stap_plan_t* plan;
+  const void* x;
+  int32_t H, W;
+  float* T;
+  uint8_t* D;
+} stap_tile;
+
+stap_status stap_run_batch(const stap_tile* tiles, int32_t ntiles, void* hip_stream);
+
+/* Library version string and the HIP device architecture the code object
+ * was built for. */
+const char* stap_version(void);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* stap_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KSTAP_H_ */

@@ -1,0 +1,241 @@
+"""Per-pixel Kronecker STAP on AMD MI355X: thin Python binding of libkstap.so.
+
+Argument marshalling only: every step of the pass runs in the library's HIP
+kernels.  PyTorch tensors supply device memory and the HIP stream.
+
+    plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4)
+    T, D = kstap.run(plan, x)          # x: torch.complex64 [p, H, W, q] on a GPU
+
+The C ABI is declared in include/kstap.h; the names here mirror it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkstap.so")
+
+STAP_OK = 0
+STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "BUSY",
+                6: "INTERNAL"}
+PRECISIONS = {"fp32": 0, "bf16x3": 1}
+STAT_MODES = {"glrt": 0, "fixed": 1}
+
+
+class StapError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class StapConfig(ctypes.Structure):
+    _fields_ = [
+        ("p", ctypes.c_int32), ("q", ctypes.c_int32), ("n", ctypes.c_int32),
+        ("stencil", ctypes.POINTER(ctypes.c_int32)),
+        ("window", ctypes.c_int32), ("guard", ctypes.c_int32),
+        ("r_a", ctypes.c_int32), ("r_b", ctypes.c_int32),
+        ("eps", ctypes.c_double), ("min_iter", ctypes.c_int32), ("max_iter", ctypes.c_int32),
+        ("stat_mode", ctypes.c_int32),
+        ("b_steer", ctypes.POINTER(ctypes.c_float)), ("h_steer", ctypes.POINTER(ctypes.c_float)),
+        ("tau", ctypes.c_double), ("pfa", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class StapProbeOut(ctypes.Structure):
+    _fields_ = [("UA", ctypes.c_void_p), ("UB", ctypes.c_void_p), ("eta", ctypes.c_void_p),
+                ("iters", ctypes.c_void_p), ("T", ctypes.c_void_p)]
+
+
+class StapTile(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("x", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
+                ("T", ctypes.c_void_p), ("D", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libkstap.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1604_03622_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    i32, p_ = ctypes.c_int32, ctypes.c_void_p
+    sigs = {
+        "stap_config_default": [ctypes.POINTER(StapConfig)],
+        "stap_plan_create": [ctypes.POINTER(StapConfig), ctypes.POINTER(p_)],
+        "stap_plan_destroy": [p_],
+        "stap_plan_info": [p_, ctypes.POINTER(ctypes.c_double)] + [ctypes.POINTER(i32)] * 5,
+        "stap_plan_stencil": [p_, ctypes.POINTER(i32)],
+        "stap_valid_region": [p_, i32, i32] + [ctypes.POINTER(i32)] * 4,
+        "stap_run": [p_, p_, i32, i32, p_, p_, p_],
+        "stap_probe": [p_, p_, i32, i32, p_, i32, ctypes.POINTER(StapProbeOut), p_],
+        "stap_run_batch": [ctypes.POINTER(StapTile), i32, p_],
+    }
+    for name, args in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.stap_last_error.restype = ctypes.c_char_p
+    L.stap_last_error.argtypes = []
+    L.stap_version.restype = ctypes.c_char_p
+    L.stap_version.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != STAP_OK:
+        raise StapError(status, lib().stap_last_error().decode())
+
+
+def _cfloat_array(values, count: int):
+    arr = np.ascontiguousarray(np.asarray(values, dtype=np.complex64).reshape(count))
+    buf = (ctypes.c_float * (2 * count))(*arr.view(np.float32).tolist())
+    return buf
+
+
+class Plan:
+    """An immutable detector plan (host only; usable on any device/stream)."""
+
+    def __init__(self, p: int, q: int, n: int, r_a: int = 1, r_b: int = 3,
+                 stencil: Optional[Sequence] = None, window: int = 0, guard: int = 3,
+                 eps: float = 1e-6, min_iter: int = 2, max_iter: int = 50,
+                 stat_mode: str = "glrt", b_steer=None, h_steer=None,
+                 tau: float = 0.0, pfa: float = 1e-4, precision: str = "fp32"):
+        L = lib()
+        cfg = StapConfig()
+        _check(L.stap_config_default(ctypes.byref(cfg)))
+        cfg.p, cfg.q, cfg.n = p, q, n
+        cfg.window, cfg.guard = window, guard
+        cfg.r_a, cfg.r_b = r_a, r_b
+        cfg.eps, cfg.min_iter, cfg.max_iter = eps, min_iter, max_iter
+        cfg.stat_mode = STAT_MODES[stat_mode]
+        cfg.tau, cfg.pfa = tau, pfa
+        cfg.precision = PRECISIONS[precision]
+        keep = []
+        if stencil is not None:
+            st = np.ascontiguousarray(np.asarray(stencil, dtype=np.int32).reshape(-1))
+            buf = (ctypes.c_int32 * st.size)(*st.tolist())
+            keep.append(buf)
+            cfg.stencil = ctypes.cast(buf, ctypes.POINTER(ctypes.c_int32))
+        if b_steer is not None:
+            buf = _cfloat_array(b_steer, q)
+            keep.append(buf)
+            cfg.b_steer = ctypes.cast(buf, ctypes.POINTER(ctypes.c_float))
+        if h_steer is not None:
+            buf = _cfloat_array(h_steer, p)
+            keep.append(buf)
+            cfg.h_steer = ctypes.cast(buf, ctypes.POINTER(ctypes.c_float))
+        handle = ctypes.c_void_p()
+        _check(L.stap_plan_create(ctypes.byref(cfg), ctypes.byref(handle)))
+        self._h = handle
+        self.p, self.q, self.n, self.r_a, self.r_b = p, q, n, r_a, r_b
+        self.precision = precision
+        tau_v = ctypes.c_double()
+        ints = [ctypes.c_int32() for _ in range(5)]
+        _check(L.stap_plan_info(self._h, ctypes.byref(tau_v), *[ctypes.byref(v) for v in ints]))
+        self.tau = tau_v.value
+        self.window = ints[0].value
+        self.extent = tuple(v.value for v in ints[1:])
+        st = (ctypes.c_int32 * (2 * n))()
+        _check(L.stap_plan_stencil(self._h, st))
+        self.stencil = np.frombuffer(st, dtype=np.int32).reshape(n, 2).copy()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def valid_region(self, H: int, W: int):
+        out = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().stap_valid_region(self._h, H, W, *[ctypes.byref(v) for v in out]))
+        return tuple(v.value for v in out)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.stap_plan_destroy(h)
+            self._h = None
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_frame(plan: Plan, x):
+    import torch
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.complex64 or not x.is_cuda:
+        raise TypeError("x must be a torch.complex64 tensor on a GPU")
+    if x.dim() != 4 or x.shape[0] != plan.p or x.shape[3] != plan.q:
+        raise ValueError(f"x must have shape [p={plan.p}, H, W, q={plan.q}], got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError("x must be contiguous")
+    return int(x.shape[1]), int(x.shape[2])
+
+
+def run(plan: Plan, x, T=None, D=None, stream=None, with_detections: bool = True):
+    """Whole-frame pass; returns (T float32 [H, W], D uint8 [H, W] or None).
+    Asynchronous on `stream` (default: torch's current stream)."""
+    import torch
+    H, W = _check_frame(plan, x)
+    if T is None:
+        T = torch.empty((H, W), dtype=torch.float32, device=x.device)
+    if D is None and with_detections:
+        D = torch.empty((H, W), dtype=torch.uint8, device=x.device)
+    _check(lib().stap_run(plan.handle, ctypes.c_void_p(x.data_ptr()), H, W, ctypes.c_void_p(T.data_ptr()),
+                          ctypes.c_void_p(D.data_ptr()) if D is not None else None, _stream_handle(stream)))
+    return T, D
+
+
+def probe(plan: Plan, x, pix, stream=None) -> dict:
+    """Per-pixel pass with intermediates for pixels pix [(r, c), ...]."""
+    import torch
+    H, W = _check_frame(plan, x)
+    dev = x.device
+    pix_t = torch.as_tensor(np.asarray(pix, dtype=np.int32).reshape(-1, 2), device=dev).contiguous()
+    npix = int(pix_t.shape[0])
+    out = dict(
+        T=torch.empty(npix, dtype=torch.float32, device=dev),
+        eta=torch.empty(npix, dtype=torch.float32, device=dev),
+        iters=torch.empty(npix, dtype=torch.int32, device=dev),
+        U_A=torch.empty((npix, plan.p, plan.r_a), dtype=torch.complex64, device=dev),
+        U_B=torch.empty((npix, plan.q, max(plan.r_b, 0)), dtype=torch.complex64, device=dev),
+    )
+    po = StapProbeOut(out["U_A"].data_ptr(), out["U_B"].data_ptr() if plan.r_b > 0 else None,
+                      out["eta"].data_ptr(), out["iters"].data_ptr(), out["T"].data_ptr())
+    _check(lib().stap_probe(plan.handle, ctypes.c_void_p(x.data_ptr()), H, W, ctypes.c_void_p(pix_t.data_ptr()),
+                            npix, ctypes.byref(po), _stream_handle(stream)))
+    out["_keep"] = pix_t
+    return out
+
+
+def run_batch(tiles, stream=None):
+    """tiles: list of (plan, x, T, D) with torch tensors; runs them in one call."""
+    arr = (StapTile * len(tiles))()
+    for i, (plan, x, T, D) in enumerate(tiles):
+        H, W = _check_frame(plan, x)
+        arr[i] = StapTile(plan.handle.value, x.data_ptr(), H, W, T.data_ptr(),
+                          D.data_ptr() if D is not None else None)
+    _check(lib().stap_run_batch(arr, len(tiles), _stream_handle(stream)))
+
+
+def version() -> str:
+    return lib().stap_version().decode()
+
+
+def exported_symbols() -> list:
+    """Names of the functions declared in include/kstap.h."""
+    import re
+    hdr = os.path.join(os.path.dirname(_HERE), "include", "kstap.h")
+    txt = open(hdr).read()
+    return sorted(set(re.findall(r"^\s*(?:stap_status|const char\*)\s+(stap_\w+)\s*\(", txt, re.M)))

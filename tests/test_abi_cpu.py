@@ -1,0 +1,74 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function declared in include/kstap.h, validates configurations, and its
+stencil / threshold / valid-region logic agrees with the oracle's independent
+implementation."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1604_03622_amd as kstap
+
+
+def test_library_exports_every_declared_symbol():
+    L = kstap.lib()
+    names = kstap.exported_symbols()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+    assert "gfx950" in kstap.version()
+
+
+@pytest.mark.parametrize("n", [64, 128, 200, 256, 17])
+def test_default_stencil_matches_oracle(n):
+    plan = kstap.Plan(p=3, q=16, n=n, r_a=1, r_b=4)
+    np.testing.assert_array_equal(plan.stencil, oracle.default_stencil(n))
+    assert plan.window == oracle.stencil_window(n)
+
+
+def test_explicit_stencil_and_valid_region():
+    st = oracle.default_stencil(40, window=12, guard=5)
+    plan = kstap.Plan(p=3, q=8, n=40, stencil=st)
+    np.testing.assert_array_equal(plan.stencil, st)
+    for H, W in ((64, 64), (20, 37), (5, 5)):
+        assert plan.valid_region(H, W) == oracle.valid_region(H, W, st)
+
+
+@pytest.mark.parametrize("p,ra,pfa", [(3, 1, 1e-4), (5, 1, 1e-4), (3, 2, 1e-3), (4, 1, 1e-6)])
+def test_threshold_matches_gamma_quantile(p, ra, pfa):
+    plan = kstap.Plan(p=p, q=8 if p != 5 else 8, n=64, r_a=ra, r_b=3, pfa=pfa) if (p, 8) in [(3, 8), (4, 8)] else None
+    if plan is None:
+        pytest.skip("no kernel instance for this (p, q)")
+    assert plan.tau == pytest.approx(oracle.gamma_upper_quantile(p - ra, pfa), rel=1e-12)
+    plan2 = kstap.Plan(p=3, q=8, n=64, tau=7.5)
+    assert plan2.tau == 7.5
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(p=0), 1), (dict(p=9), 1), (dict(q=1), 1), (dict(q=33), 1), (dict(n=0), 1), (dict(n=257), 1),
+    (dict(r_a=0), 1), (dict(r_a=4), 1), (dict(r_b=9), 1), (dict(min_iter=0), 1), (dict(min_iter=5, max_iter=4), 1),
+    (dict(guard=2), 1), (dict(window=11), 1), (dict(window=10, n=100), 1), (dict(pfa=0.0), 1),
+    (dict(stat_mode="fixed"), 1), (dict(stencil=[[0, 0]] * 64), 1), (dict(stencil=[[1, 2]] * 64), 1),
+    (dict(p=7, q=16), 2), (dict(p=1), 2),
+])
+def test_plan_validation_errors(kw, status):
+    args = dict(p=3, q=8, n=64, r_a=1, r_b=3)
+    args.update(kw)
+    with pytest.raises(kstap.StapError) as ei:
+        kstap.Plan(**args)
+    assert ei.value.status == status
+    assert kstap.lib().stap_last_error().decode() != ""
+
+
+def test_run_rejects_bad_arguments_without_touching_a_device():
+    plan = kstap.Plan(p=3, q=8, n=64)
+    L = kstap.lib()
+    assert L.stap_run(plan.handle, None, 64, 64, ctypes.c_void_p(16), None, None) == 1
+    assert L.stap_run(plan.handle, ctypes.c_void_p(16), 0, 64, ctypes.c_void_p(16), None, None) == 1
+    assert L.stap_run(plan.handle, ctypes.c_void_p(16), 64, 64, None, None, None) == 1
+    assert L.stap_run(plan.handle, ctypes.c_void_p(16), 40000, 40000, ctypes.c_void_p(16), None, None) == 1
+    assert L.stap_run(None, ctypes.c_void_p(16), 64, 64, ctypes.c_void_p(16), None, None) == 1
+    out = kstap.StapProbeOut(None, None, None, None, None)
+    assert L.stap_probe(plan.handle, ctypes.c_void_p(16), 64, 64, ctypes.c_void_p(16), 3, ctypes.byref(out), None) == 1
+    assert L.stap_probe(plan.handle, ctypes.c_void_p(16), 64, 64, None, -1, None, None) == 1
