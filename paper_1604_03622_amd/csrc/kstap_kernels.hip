@@ -16,9 +16,12 @@
 //   a5  LR-Kron (Algorithm 2) on the LDS-resident S: one sweep over S per
 //       iteration computes the residual of the previous iterate, the new time
 //       factor b = R^T conj(a) / ||a||^2 and the partial sums of R conj(b).
-//       EIG_{r_a} (Eq. (17)) by subspace iteration with a warm start.
-//   a6  final b = R^T conj(a) / ||a||^2, Hermitian part, top-r_b subspace by
-//       subspace iteration (CholQR2 orthonormalisation, residual stop).
+//       EIG_{r_a} (Eq. (17)): power iteration for r_a = 1, subspace
+//       iteration otherwise, warm-started from the previous iterate.
+//   a6  final b = R^T conj(a) / ||a||^2 and its Hermitian part are queued
+//       in registers; every 64/q' pixels (q' = q rounded up to 8, 16 or 32)
+//       one batched subspace iteration finds the top-r_b subspaces, q' lanes
+//       per pixel with group-local DPP reductions (CholQR2, residual stop).
 //   a8  T = ||F_A X conj(F_B b_s)||^2 / (b_s^H F_B b_s) (Sec. 5, Eq. (25);
 //       Sec. 6.3, Eq. (26)); D = T > tau.
 
@@ -50,27 +53,72 @@ __device__ __forceinline__ float2 ccfma(float2 a, float2 b, float2 c) {
 }
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) { return cfma(a, b, cz()); }
 
+// double2 versions (FP64 eigensolves and normalisation of the mixed path)
+template <typename C> __device__ __forceinline__ C czero();
+template <> __device__ __forceinline__ float2 czero<float2>() { return make_float2(0.f, 0.f); }
+template <> __device__ __forceinline__ double2 czero<double2>() { return make_double2(0.0, 0.0); }
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double cabs2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+__device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 c) {
+  return make_double2(fma(a.x, b.x, fma(-a.y, b.y, c.x)), fma(a.x, b.y, fma(a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 ccfma(double2 a, double2 b, double2 c) {
+  return make_double2(fma(a.x, b.x, fma(a.y, b.y, c.x)), fma(a.x, b.y, fma(-a.y, b.x, c.y)));
+}
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) { return cfma(a, b, czero<double2>()); }
+template <typename C> __device__ __forceinline__ C cto(float2 a);
+template <> __device__ __forceinline__ float2 cto<float2>(float2 a) { return a; }
+template <> __device__ __forceinline__ double2 cto<double2>(float2 a) { return make_double2(a.x, a.y); }
+__device__ __forceinline__ float2 tof(float2 a) { return a; }
+__device__ __forceinline__ float2 tof(double2 a) { return make_float2(float(a.x), float(a.y)); }
+__device__ __forceinline__ float xsqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double xsqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float xmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double xmax(double a, double b) { return fmax(a, b); }
+
 // ------------------------------------------------------- wavefront reductions
-// Sum over the 64 lanes, result in every lane: four DPP steps inside each
-// 16-lane row (quad swaps, half-row mirror, row mirror), then two lane
-// permutes across rows.
-template <int CTRL>
+// Sum over the 64 lanes.  Four DPP steps reduce each 16-lane row (quad swaps,
+// half-row mirror, row mirror: every lane then holds its row's sum), two
+// row broadcasts (lane 15 -> next row, lane 31 -> rows 2 and 3) accumulate
+// the rows into lane 63, and the total is read from lane 63 as a uniform
+// value.  No LDS traffic.
+template <int CTRL, int ROWS>
 __device__ __forceinline__ float dpp(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROWS, 0xF, false));
 }
 __device__ __forceinline__ float wsum(float v) {
-  v += dpp<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp<0x141>(v);  // row_half_mirror
-  v += dpp<0x140>(v);  // row_mirror
-  v += __shfl_xor(v, 16);
-  v += __shfl_xor(v, 32);
-  return v;
+  v += dpp<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  v += dpp<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  v += dpp<0x141, 0xF>(v);   // row_half_mirror
+  v += dpp<0x140, 0xF>(v);   // row_mirror
+  v += dpp<0x142, 0xA>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp<0x143, 0xC>(v);   // row_bcast:31 into rows 2 and 3
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 __device__ __forceinline__ float2 wsum(float2 v) { return make_float2(wsum(v.x), wsum(v.y)); }
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dppd(double v) {
+  const int2 i = __builtin_bit_cast(int2, v);
+  int2 o;
+  o.x = __builtin_amdgcn_update_dpp(0, i.x, CTRL, ROWS, 0xF, false);
+  o.y = __builtin_amdgcn_update_dpp(0, i.y, CTRL, ROWS, 0xF, false);
+  return __builtin_bit_cast(double, o);
+}
 __device__ __forceinline__ double wsumd(double v) {
-  for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o);
-  return v;
+  v += dppd<0xB1, 0xF>(v);
+  v += dppd<0x4E, 0xF>(v);
+  v += dppd<0x141, 0xF>(v);
+  v += dppd<0x140, 0xF>(v);
+  v += dppd<0x142, 0xA>(v);
+  v += dppd<0x143, 0xC>(v);
+  const int2 i = __builtin_bit_cast(int2, v);
+  int2 o;
+  o.x = __builtin_amdgcn_readlane(i.x, 63);
+  o.y = __builtin_amdgcn_readlane(i.y, 63);
+  return __builtin_bit_cast(double, o);
 }
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }   // one-wave workgroups
@@ -83,225 +131,204 @@ __device__ __forceinline__ float2 omega(int k, int c) {
   return make_float2(__cosf(ph), __sinf(ph));
 }
 
+// Sum over each group of QP consecutive lanes (QP = 8, 16, 32 or 64); every
+// lane of a group receives its group's sum (QP = 64: a uniform value).
+template <int QP>
+__device__ __forceinline__ float gsum(float v) {
+  if constexpr (QP == 64) {
+    return wsum(v);
+  } else {
+    v += dpp<0xB1, 0xF>(v);
+    v += dpp<0x4E, 0xF>(v);
+    v += dpp<0x141, 0xF>(v);
+    if constexpr (QP >= 16) v += dpp<0x140, 0xF>(v);
+    if constexpr (QP == 32) v += __shfl_xor(v, 16);
+    return v;
+  }
+}
+template <int QP>
+__device__ __forceinline__ float2 gsum(float2 v) { return make_float2(gsum<QP>(v.x), gsum<QP>(v.y)); }
+template <int QP>
+__device__ __forceinline__ double gsum(double v) {
+  if constexpr (QP == 64) {
+    return wsumd(v);
+  } else {
+    v += dppd<0xB1, 0xF>(v);
+    v += dppd<0x4E, 0xF>(v);
+    v += dppd<0x141, 0xF>(v);
+    if constexpr (QP >= 16) v += dppd<0x140, 0xF>(v);
+    if constexpr (QP == 32) v += __shfl_xor(v, 16);
+    return v;
+  }
+}
+template <int QP>
+__device__ __forceinline__ double2 gsum(double2 v) { return make_double2(gsum<QP>(v.x), gsum<QP>(v.y)); }
+
 // ------------------------------------------------- small Hermitian subspaces
-// Orthonormalise the rows held by the lanes (lane k < d holds row k of a
-// d x r block W) by Cholesky QR: G = W^H W = L L^H, V = W L^{-H}.
-template <int RM>
-__device__ __forceinline__ void chol_qr(float2 (&w)[RM], int r, bool act) {
-  float2 G[RM][RM];
+// Lanes are split into groups of QP; in each group lane k (< d) holds row k of
+// a d x r block W.  Orthonormalise the columns inside every group by
+// classical Gram-Schmidt with one re-orthogonalisation pass (CGS2).
+template <typename S> __device__ __forceinline__ S tiny();
+template <> __device__ __forceinline__ float tiny<float>() { return 1e-30f; }
+template <> __device__ __forceinline__ double tiny<double>() { return 1e-280; }
+
+template <int RM, int QP, typename C>
+__device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
+  using S = decltype(C{}.x);
 #pragma unroll
-  for (int a = 0; a < RM; ++a)
+  for (int c = 0; c < RM; ++c) {
+    if (c >= r) continue;
 #pragma unroll
-    for (int b = a; b < RM; ++b) {
-      if (a < r && b < r) {
-        float2 g = act ? ccfma(w[a], w[b], cz()) : cz();
-        G[a][b] = wsum(g);
-      } else {
-        G[a][b] = cz();
+    for (int pass = 0; pass < 2; ++pass) {
+      C h[RM];
+#pragma unroll
+      for (int a = 0; a < c; ++a) h[a] = gsum<QP>(act ? ccfma(w[a], w[c], czero<C>()) : czero<C>());
+      if (act) {
+#pragma unroll
+        for (int a = 0; a < c; ++a) w[c] = csub(w[c], cmul(w[a], h[a]));
       }
     }
-  float2 L[RM][RM];
-  float dinv[RM];
-  float tr = 0.f;
-#pragma unroll
-  for (int a = 0; a < RM; ++a) tr += (a < r) ? G[a][a].x : 0.f;
-#pragma unroll
-  for (int j = 0; j < RM; ++j) {
-    if (j >= r) { dinv[j] = 0.f; continue; }
-    float dj = G[j][j].x;
-#pragma unroll
-    for (int a = 0; a < j; ++a) dj -= cabs2(L[j][a]);
-    dj = fmaxf(dj, 1e-30f + 1e-14f * tr);
-    const float ljj = sqrtf(dj);
-    dinv[j] = 1.f / ljj;
-    L[j][j] = make_float2(ljj, 0.f);
-#pragma unroll
-    for (int i = j + 1; i < RM; ++i) {
-      if (i >= r) continue;
-      float2 s = cconj(G[j][i]);   // G[i][j]
-#pragma unroll
-      for (int a = 0; a < j; ++a) s = csub(s, cmul(L[i][a], cconj(L[j][a])));
-      L[i][j] = cscale(s, dinv[j]);
-    }
-  }
-  if (act) {
-#pragma unroll
-    for (int c = 0; c < RM; ++c) {
-      if (c >= r) continue;
-      float2 s = w[c];
-#pragma unroll
-      for (int a = 0; a < c; ++a) s = csub(s, cmul(w[a], cconj(L[c][a])));
-      w[c] = cscale(s, dinv[c]);
-    }
+    const S nn = gsum<QP>(act ? cabs2(w[c]) : S(0));
+    const S inv = S(1) / xsqrt(xmax(nn, tiny<S>()));
+    w[c] = act ? cscale(w[c], inv) : czero<C>();
   }
 }
 
-// Top-r invariant subspace of the Hermitian d x d matrix M (LDS, row-major)
-// by subspace iteration.  Lane k < d holds row k of the orthonormal basis v.
-// `cold` starts from M * Omega; otherwise v is the warm start.  Stops `extra`
-// steps after ||M V - V (V^H M V)||_F <= tol ||M V||_F, or after max_steps.
-template <int RM>
-__device__ int top_subspace(const float2* M, int d, int r, float2 (&v)[RM], float2* sV,
-                            bool cold, int max_steps, float tol, int extra) {
-  const int k = threadIdx.x;
-  const bool act = k < d;
+// Top-r invariant subspace of one Hermitian D x D matrix per lane group by
+// subspace iteration.  Lane k of a group holds row k of the matrix (mrow) and
+// row k of the orthonormal basis v (CGS2 orthonormalisation).  `cold` starts from M * Omega (Omega a
+// fixed generic block); otherwise v is the warm start.  A group has converged
+// when ||M V - V (V^H M V)||_F <= tol ||M V||_F for the basis entering a step;
+// that step's orthonormalised M V is kept.  The loop runs until every group
+// has converged or max_steps.  sV: LDS scratch of RM * D * (64 / QP) float2.
+template <int RM, int QP, int D, typename C>
+__device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_ok, int r, C (&v)[RM],
+                                              C* sV, bool cold, int max_steps, double tol) {
+  using S = decltype(C{}.x);
+  constexpr int G = 64 / QP;
+  const int lane = threadIdx.x, g = lane / QP, k = lane % QP;
   if (cold) {
 #pragma unroll
-    for (int c = 0; c < RM; ++c) v[c] = (act && c < r) ? omega(k, c) : cz();
+    for (int c = 0; c < RM; ++c) v[c] = (row_ok && c < r) ? cto<C>(omega(k, c)) : czero<C>();
   }
-  bool ortho = !cold;
-  int step = 0, after = -1;
+  bool tested = !cold;
+  int step = 0;
   while (true) {
-    if (act) {
+    if (row_ok) {
 #pragma unroll
       for (int c = 0; c < RM; ++c)
-        if (c < r) sV[c * d + k] = v[c];
+        if (c < r) sV[(c * D + k) * G + g] = v[c];
     }
     wave_sync();
-    float2 w[RM];
+    C w[RM];
 #pragma unroll
-    for (int c = 0; c < RM; ++c) w[c] = cz();
-    if (act) {
-      for (int l = 0; l < d; ++l) {
-        const float2 m = M[k * d + l];
+    for (int c = 0; c < RM; ++c) w[c] = czero<C>();
+    if (row_ok) {
+#pragma unroll
+      for (int l = 0; l < D; ++l) {
 #pragma unroll
         for (int c = 0; c < RM; ++c)
-          if (c < r) w[c] = cfma(m, sV[c * d + l], w[c]);
+          if (c < r) w[c] = cfma(cto<C>(mrow[l]), sV[(c * D + l) * G + g], w[c]);
       }
     }
     wave_sync();
     bool conv = false;
-    if (ortho) {
-      // H = V^H W (Hermitian), residual W - V H
-      float2 Hm[RM][RM];
+    if (tested) {
+      // residual W - V (V^H W), one column at a time
+      S rn = 0, wn = 0;
 #pragma unroll
-      for (int a = 0; a < RM; ++a)
+      for (int b = 0; b < RM; ++b) {
+        if (b >= r) continue;
+        C hb[RM];
 #pragma unroll
-        for (int b = a; b < RM; ++b) {
-          if (a < r && b < r) {
-            Hm[a][b] = wsum(act ? ccfma(v[a], w[b], cz()) : cz());
-            Hm[b][a] = cconj(Hm[a][b]);
-          }
-        }
-      float rn = 0.f, wn = 0.f;
-      if (act) {
-#pragma unroll
-        for (int b = 0; b < RM; ++b) {
-          if (b >= r) continue;
-          float2 rr = w[b];
+        for (int a = 0; a < RM; ++a)
+          if (a < r) hb[a] = gsum<QP>(row_ok ? ccfma(v[a], w[b], czero<C>()) : czero<C>());
+        if (row_ok) {
+          C rr = w[b];
 #pragma unroll
           for (int a = 0; a < RM; ++a)
-            if (a < r) rr = csub(rr, cmul(v[a], Hm[a][b]));
+            if (a < r) rr = csub(rr, cmul(v[a], hb[a]));
           rn += cabs2(rr);
           wn += cabs2(w[b]);
         }
       }
-      rn = wsum(rn);
-      wn = wsum(wn);
-      conv = rn <= tol * tol * wn;
+      rn = gsum<QP>(rn);
+      wn = gsum<QP>(wn);
+      conv = rn <= S(tol * tol) * wn;
     }
-    chol_qr<RM>(w, r, act);
-    chol_qr<RM>(w, r, act);
+    orth_cgs2<RM, QP, C>(w, r, row_ok);
 #pragma unroll
     for (int c = 0; c < RM; ++c) v[c] = w[c];
-    ortho = true;
+    tested = true;
     ++step;
-    if (conv && after < 0) after = 0;
-    if (after >= 0) {
-      if (after >= extra) break;
-      ++after;
-    }
-    if (step >= max_steps) break;
+    const bool all = __ballot(!conv) == 0;
+    if (all || step >= max_steps) break;
   }
   return step;
 }
 
-// ------------------------------------------------------------ kernel body
-template <int P, int Q, int RBM, int MODE>
-__global__ __launch_bounds__(64) void kstap_fp32_kernel(const KParams prm) {
-  constexpr int PQ = P * Q;
-  constexpr int NB = (PQ + 15) / 16;        // 16-row blocks of the pq x pq covariance
-  constexpr int NT = NB * (NB + 1) / 2;     // upper tiles of Re S
-  constexpr int NO = NB * (NB - 1) / 2;     // strictly upper tiles of Im S
-  constexpr int QQ = Q * Q;
-  constexpr int NE = (QQ + 63) / 64;        // q x q entries per lane
-  constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
-  static_assert(PQ * PQ >= 2 * QQ + RBM * Q, "LDS reuse needs p >= 2");
-
-  __shared__ float2 sS[PQ * PQ];
-  __shared__ int sOff[kMaxN];
-  __shared__ float2 sA[P * P];
-  __shared__ float2 sUA[P * RAM];
-  __shared__ float2 sVa[P * RAM];
-
-  const int lane = threadIdx.x;
-  const int n = prm.n;
-  const int H = prm.H, W = prm.W;
-  const int r_a = prm.r_a, r_b = prm.r_b;
-
-  for (int m = lane; m < n; m += 64) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
-  wave_sync();
-
-  // Operand rows of this lane: row rho = 16*I + (lane & 15) of the stacked
-  // snapshot, channel rho / q, sample rho % q.
-  int chan_off[NB];
-  bool row_ok[NB];
+// Dominant eigenvector of a Hermitian P x P matrix held identically by every
+// lane (power iteration; stop on ||M u - (u^H M u) u|| <= tol ||M u||).
+template <int P, typename C>
+__device__ __forceinline__ void power_top(const C (&M)[P * P], C (&u)[P], bool cold, int max_steps, double tol) {
+  using S = decltype(C{}.x);
+  if (cold) {
+    int jb = 0;
+    S db = M[0].x;
 #pragma unroll
-  for (int I = 0; I < NB; ++I) {
-    const int rho = 16 * I + (lane & 15);
-    row_ok[I] = rho < PQ;
-    const int ch = rho / Q, j = rho - ch * Q;
-    chan_off[I] = row_ok[I] ? ch * H * W * Q + j : 0;
-  }
-
-  // pixel schedule
-  int64_t first, count;
-  if (MODE == kModeRun) {
-    const int per = gridDim.x >> 3;   // grid is a multiple of 8 (one share per XCD)
-    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (logical >= prm.nlogical) return;
-    const int64_t total = int64_t(H) * W;
-    first = int64_t(logical) * prm.pix_per_block;
-    count = total - first;
-    if (count > prm.pix_per_block) count = prm.pix_per_block;
-  } else {
-    first = int64_t(blockIdx.x) * prm.pix_per_block;
-    count = prm.npix - first;
-    if (count > prm.pix_per_block) count = prm.pix_per_block;
-  }
-
-  for (int64_t it = 0; it < count; ++it) {
-    const int64_t idx = first + it;
-    int r, c;
-    if (MODE == kModeRun) {
-      r = int(idx / W);
-      c = int(idx - int64_t(r) * W);
-    } else {
-      r = prm.pix[2 * idx];
-      c = prm.pix[2 * idx + 1];
-    }
-    const bool valid = r >= prm.r0 && r < prm.r1 && c >= prm.c0 && c < prm.c1;
-    const int64_t out_idx = idx;
-    if (!valid) {
-      if (lane == 0) {
-        prm.T[out_idx] = 0.f;
-        if (MODE == kModeRun && prm.D) prm.D[out_idx] = 0;
-        if (MODE == kModeProbe) {
-          if (prm.eta) prm.eta[idx] = 0.f;
-          if (prm.iters) prm.iters[idx] = 0;
-        }
+    for (int j = 1; j < P; ++j)
+      if (M[j * P + j].x > db) {
+        db = M[j * P + j].x;
+        jb = j;
       }
-      if (MODE == kModeProbe) {
-        if (prm.UA)
-          for (int e = lane; e < P * r_a; e += 64) prm.UA[idx * P * r_a + e] = cz();
-        if (prm.UB)
-          for (int e = lane; e < Q * r_b; e += 64) prm.UB[idx * Q * r_b + e] = cz();
-      }
-      continue;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      C s = czero<C>();
+#pragma unroll
+      for (int j = 0; j < P; ++j) s = (j == jb) ? M[i * P + j] : s;
+      u[i] = s;
     }
-    const float2* xp = prm.x + (int64_t(r) * W + c) * Q;
+    S nn = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) nn += cabs2(u[i]);
+    const S inv = nn > S(0) ? S(1) / xsqrt(nn) : S(0);
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[i] = cscale(u[i], inv);
+  }
+  for (int step = 0; step < max_steps; ++step) {
+    C w[P];
+    S lam = 0, wn = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      C s = czero<C>();
+#pragma unroll
+      for (int j = 0; j < P; ++j) s = cfma(M[i * P + j], u[j], s);
+      w[i] = s;
+      lam += u[i].x * s.x + u[i].y * s.y;
+      wn += cabs2(s);
+    }
+    S rn = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) rn += cabs2(csub(w[i], cscale(u[i], lam)));
+    if (!(wn > S(0))) break;
+    const S inv = S(1) / xsqrt(wn);
+#pragma unroll
+    for (int i = 0; i < P; ++i) u[i] = cscale(w[i], inv);
+    if (rn <= S(tol * tol) * wn) break;
+  }
+}
 
-    // ---------------------------------------------------------------- a2 SCM
+// ------------------------------------------------------------ a2, FP32
+// S = (1/n) sum_m x_m x_m^H of one pixel on v_mfma_f32_16x16x4_f32, written
+// to LDS as the full Hermitian pq x pq matrix (row-major).
+template <int P, int Q>
+__device__ __forceinline__ void scm_fp32(const float2* __restrict__ xp, const int* sOff, const int (&chan_off)[(P * Q + 15) / 16],
+                                         const bool (&row_ok)[(P * Q + 15) / 16], int n, float2* sS) {
+  constexpr int PQ = P * Q;
+  constexpr int NB = (PQ + 15) / 16;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int NO = NB * (NB - 1) / 2;
+  const int lane = threadIdx.x;
     f4 accR[NT], accI[NO > 0 ? NO : 1], accD[NB];
 #pragma unroll
     for (int t = 0; t < NT; ++t) accR[t] = f4{0.f, 0.f, 0.f, 0.f};
@@ -311,48 +338,65 @@ __global__ __launch_bounds__(64) void kstap_fp32_kernel(const KParams prm) {
     for (int t = 0; t < NB; ++t) accD[t] = f4{0.f, 0.f, 0.f, 0.f};
 
     const int nch = (n + 3) >> 2;
-    float2 cur[NB], nxt[NB];
-    {
-      const int m = lane >> 4;
+    // operand ring: chunk ch lives in slot ch % PF; PF - 1 chunks in flight
+    constexpr int PF = 4;
+    float2 ring[PF][NB];
+    auto fetch = [&](int ch, float2 (&v)[NB]) {
+      const int m = ch * 4 + (lane >> 4);
       const bool mok = m < n;
       const int off = sOff[mok ? m : 0];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) cur[I] = (mok && row_ok[I]) ? xp[chan_off[I] + off] : cz();
-    }
-    for (int ch = 0; ch < nch; ++ch) {
-      {
-        const int m = (ch + 1) * 4 + (lane >> 4);
-        const bool mok = m < n;
-        const int off = sOff[mok ? m : 0];
+      for (int I = 0; I < NB; ++I) v[I] = (mok && row_ok[I]) ? xp[chan_off[I] + off] : cz();
+    };
 #pragma unroll
-        for (int I = 0; I < NB; ++I) nxt[I] = (mok && row_ok[I]) ? xp[chan_off[I] + off] : cz();
-      }
-      float xr[NB], xi[NB], nxr[NB];
+    for (int s0 = 0; s0 < PF - 1; ++s0) fetch(s0, ring[s0]);
+    for (int ch0 = 0; ch0 < nch; ch0 += PF) {
 #pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        xr[I] = cur[I].x;
-        xi[I] = cur[I].y;
-        nxr[I] = -cur[I].x;
-      }
-      int t = 0, u = 0;
+      for (int sl = 0; sl < PF; ++sl) {
+        const int ch = ch0 + sl;
+        fetch(ch + PF - 1, ring[(sl + PF - 1) % PF]);
+        if (ch < nch) {
+          float xr[NB], xi[NB], nxr[NB];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) {
-#pragma unroll
-        for (int J = I; J < NB; ++J) {
-          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[I], xr[J], accR[t], 0, 0, 0);
-          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xi[J], accR[t], 0, 0, 0);
-          if (J > I) {
-            accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[J], accI[u], 0, 0, 0);
-            accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(nxr[I], xi[J], accI[u], 0, 0, 0);
-            ++u;
-          } else {
-            accD[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[I], accD[I], 0, 0, 0);
+          for (int I = 0; I < NB; ++I) {
+            xr[I] = ring[sl][I].x;
+            xi[I] = ring[sl][I].y;
+            nxr[I] = -ring[sl][I].x;
           }
-          ++t;
+          // first product of every accumulator, then the second: no two
+          // consecutive MFMAs write the same accumulator
+          {
+            int t = 0, u = 0;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+              for (int J = I; J < NB; ++J) {
+                accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[I], xr[J], accR[t], 0, 0, 0);
+                if (J > I) {
+                  accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[J], accI[u], 0, 0, 0);
+                  ++u;
+                } else {
+                  accD[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[I], accD[I], 0, 0, 0);
+                }
+                ++t;
+              }
+          }
+          {
+            int t = 0, u = 0;
+#pragma unroll
+            for (int I = 0; I < NB; ++I)
+#pragma unroll
+              for (int J = I; J < NB; ++J) {
+                accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xi[J], accR[t], 0, 0, 0);
+                if (J > I) {
+                  accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(nxr[I], xi[J], accI[u], 0, 0, 0);
+                  ++u;
+                }
+                ++t;
+              }
+          }
         }
       }
-#pragma unroll
-      for (int I = 0; I < NB; ++I) cur[I] = nxt[I];
     }
 
     // S to LDS, full Hermitian, scaled by 1/n.  MFMA output layout: lane l,
@@ -405,6 +449,365 @@ __global__ __launch_bounds__(64) void kstap_fp32_kernel(const KParams prm) {
     }
     wave_sync();
 
+}
+
+// -------------------------------------------------------- a2, split BF16
+// The same S from three BF16 products per tile: x = hi + lo with
+// hi = bf16(x), lo = bf16(x - hi); S ~ hi hi^H + hi lo^H + lo hi^H with FP32
+// accumulation on v_mfma_f32_16x16x32_bf16.  One instruction covers 16
+// training vectors: in each 16-lane group g, element 2v + part of a lane's
+// 8-element operand is (re, im) of vector 4g + v of the chunk.  Re S tiles
+// take Y_I Y_J^T with Y = (re, im) pairs; Im S tiles take Z_I Y_J^T with
+// Z = (im, -re) pairs (a half-word rotate and a sign flip of Y's bits).
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void split_bf16(const float2 (&v)[4], bf8& hi, bf8& lo) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float a = v[e].x, b = v[e].y;
+    const __bf16 ha = (__bf16)a, hb = (__bf16)b;
+    hi[2 * e] = ha;
+    hi[2 * e + 1] = hb;
+    lo[2 * e] = (__bf16)(a - (float)ha);
+    lo[2 * e + 1] = (__bf16)(b - (float)hb);
+  }
+}
+__device__ __forceinline__ bf8 swap_neg(bf8 y) {
+  u4 w = __builtin_bit_cast(u4, y);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) w[e] = ((w[e] >> 16) | (w[e] << 16)) ^ 0x80000000u;
+  return __builtin_bit_cast(bf8, w);
+}
+
+template <int P, int Q>
+__device__ __forceinline__ void scm_bf16x3(const float2* __restrict__ xp, const int* sOff, const int (&chan_off)[(P * Q + 15) / 16],
+                                           const bool (&row_ok)[(P * Q + 15) / 16], int n, float2* sS) {
+  constexpr int PQ = P * Q;
+  constexpr int NB = (PQ + 15) / 16;
+  constexpr int NT = NB * (NB + 1) / 2;
+  const int lane = threadIdx.x;
+  f4 accR[NT], accI[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) accR[t] = accI[t] = f4{0.f, 0.f, 0.f, 0.f};
+  const int nch = (n + 15) >> 4;
+  constexpr int PF = 2;
+  float2 ring[PF][NB][4];
+  auto fetch = [&](int ch, float2 (&v)[NB][4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int m = ch * 16 + 4 * (lane >> 4) + e;
+      const bool mok = m < n;
+      const int off = sOff[mok ? m : 0];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) v[I][e] = (mok && row_ok[I]) ? xp[chan_off[I] + off] : cz();
+    }
+  };
+#pragma unroll
+  for (int s0 = 0; s0 < PF - 1; ++s0) fetch(s0, ring[s0]);
+  for (int ch0 = 0; ch0 < nch; ch0 += PF) {
+#pragma unroll
+    for (int sl = 0; sl < PF; ++sl) {
+      const int ch = ch0 + sl;
+      fetch(ch + PF - 1, ring[(sl + PF - 1) % PF]);
+      if (ch < nch) {
+        bf8 hi[NB], lo[NB];
+#pragma unroll
+        for (int I = 0; I < NB; ++I) split_bf16(ring[sl][I], hi[I], lo[I]);
+        {
+          int t = 0;
+#pragma unroll
+          for (int I = 0; I < NB; ++I) {
+            const bf8 zh = swap_neg(hi[I]);
+#pragma unroll
+            for (int J = I; J < NB; ++J, ++t) {
+              accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], hi[J], accR[t], 0, 0, 0);
+              accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, hi[J], accI[t], 0, 0, 0);
+            }
+          }
+        }
+        {
+          int t = 0;
+#pragma unroll
+          for (int I = 0; I < NB; ++I) {
+            const bf8 zh = swap_neg(hi[I]);
+#pragma unroll
+            for (int J = I; J < NB; ++J, ++t) {
+              accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], lo[J], accR[t], 0, 0, 0);
+              accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, lo[J], accI[t], 0, 0, 0);
+            }
+          }
+        }
+        {
+          int t = 0;
+#pragma unroll
+          for (int I = 0; I < NB; ++I) {
+            const bf8 zl = swap_neg(lo[I]);
+#pragma unroll
+            for (int J = I; J < NB; ++J, ++t) {
+              accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[I], hi[J], accR[t], 0, 0, 0);
+              accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, hi[J], accI[t], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+  const float inv_n = 1.f / float(n);
+  const int trow = 4 * (lane >> 4), tcol = lane & 15;
+  int t = 0;
+#pragma unroll
+  for (int I = 0; I < NB; ++I)
+#pragma unroll
+    for (int J = I; J < NB; ++J, ++t)
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        const int row = 16 * I + trow + q4, col = 16 * J + tcol;
+        if (row < PQ && col < PQ) {
+          const float re = accR[t][q4] * inv_n, im = accI[t][q4] * inv_n;
+          sS[row * PQ + col] = make_float2(re, im);
+          if (J > I) sS[col * PQ + row] = make_float2(re, -im);
+        }
+      }
+  wave_sync();
+}
+
+// ------------------------------------------------------------ kernel body
+template <int Q>
+struct Groups {
+  static constexpr int QP = (Q <= 8) ? 8 : (Q <= 16) ? 16 : (Q <= 32) ? 32 : 64;
+  static constexpr int G = 64 / QP;
+};
+
+template <bool B, typename T, typename F> struct Pick { using type = T; };
+template <typename T, typename F> struct Pick<false, T, F> { using type = F; };
+
+// PREC 0: FP32 covariance, FP32 eigensolves and statistic.
+// PREC 1: split-BF16 covariance, FP64 eigensolves and statistic.
+template <int P, int Q, int RBM, int MODE, int PREC>
+__global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
+  using EC = typename Pick<PREC == 1, double2, float2>::type;   // eigensolver / statistic precision
+  using ES = decltype(EC{}.x);
+  constexpr int PQ = P * Q;
+  constexpr int NB = (PQ + 15) / 16;        // 16-row blocks of the pq x pq covariance
+  constexpr int NT = NB * (NB + 1) / 2;     // upper tiles of Re S
+  constexpr int NO = NB * (NB - 1) / 2;     // strictly upper tiles of Im S
+  constexpr int QQ = Q * Q;
+  constexpr int NE = (QQ + 63) / 64;        // q x q entries per lane
+  constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
+  constexpr int QP = Groups<Q>::QP;         // lanes per pixel in the batched tail
+  constexpr int G = Groups<Q>::G;           // pixels per batched tail
+  static_assert(PQ * PQ >= QQ, "LDS reuse");
+  constexpr bool kTailInS = sizeof(EC) * RBM * Q * G <= sizeof(float2) * PQ * PQ;
+
+  __shared__ float2 sS[PQ * PQ];            // S; then raw B; then tail scratch
+  __shared__ int sOff[kMaxN];
+  __shared__ float2 sA[P * P];
+  __shared__ EC sUA[P * RAM];
+  __shared__ EC sAh[P * P];
+  __shared__ EC sVa[P * RAM];
+  __shared__ EC sQUA[G][P * RAM];           // queued pixels: U_A
+  __shared__ EC sVt[kTailInS ? 1 : RBM * Q * G];
+  EC* const tail_scratch = kTailInS ? reinterpret_cast<EC*>(sS) : sVt;
+  __shared__ int64_t sQidx[G];              //                pixel index
+  __shared__ int sQflag[G];                 //                0 ok, 1 zero training, 2 non-finite
+  __shared__ float sQeta[G];
+  __shared__ int sQit[G];
+
+  const int lane = threadIdx.x;
+  const int n = prm.n;
+  const int H = prm.H, W = prm.W;
+  const int r_a = prm.r_a, r_b = prm.r_b;
+
+  for (int m = lane; m < n; m += 64) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
+  wave_sync();
+
+  // Operand rows of this lane: row rho = 16*I + (lane & 15) of the stacked
+  // snapshot, channel rho / q, sample rho % q.
+  int chan_off[NB];
+  bool row_ok[NB];
+#pragma unroll
+  for (int I = 0; I < NB; ++I) {
+    const int rho = 16 * I + (lane & 15);
+    row_ok[I] = rho < PQ;
+    const int ch = rho / Q, j = rho - ch * Q;
+    chan_off[I] = row_ok[I] ? ch * H * W * Q + j : 0;
+  }
+
+  // pixel schedule
+  int64_t first, count;
+  if (MODE == kModeRun) {
+    const int per = gridDim.x >> 3;   // grid is a multiple of 8 (one share per XCD)
+    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (logical >= prm.nlogical) return;
+    const int64_t total = int64_t(H) * W;
+    first = int64_t(logical) * prm.pix_per_block;
+    count = total - first;
+    if (count > prm.pix_per_block) count = prm.pix_per_block;
+  } else {
+    first = int64_t(blockIdx.x) * prm.pix_per_block;
+    count = prm.npix - first;
+    if (count > prm.pix_per_block) count = prm.pix_per_block;
+  }
+
+  // queue of pixels waiting for the batched tail: lane (g, k) holds row k of
+  // the Hermitian time factor of queued pixel g
+  const int tg = lane / QP, tk = lane % QP;
+  float2 Bq[Q];
+#pragma unroll
+  for (int l = 0; l < Q; ++l) Bq[l] = cz();
+  int nq = 0;
+
+  // ------------------------------------------------ a6 + a8 for G pixels
+  auto tail = [&](int nfill) {
+    const bool slot_ok = tg < nfill;
+    const bool rok = slot_ok && tk < Q;
+    const int flag = slot_ok ? sQflag[tg] : 1;
+    const int64_t pidx = slot_ok ? sQidx[tg] : 0;
+    EC vb[RBM];
+#pragma unroll
+    for (int c = 0; c < RBM; ++c) vb[c] = czero<EC>();
+    if (r_b > 0)
+      group_subspace<RBM, QP, Q, EC>(Bq, rok && flag == 0, r_b, vb, tail_scratch, true, 200, PREC ? 1e-12 : 2e-6);
+    // statistic
+    int pr, pc;
+    if (MODE == kModeRun) {
+      pr = int(pidx / W);
+      pc = int(pidx - int64_t(pr) * W);
+    } else {
+      pr = prm.pix[2 * pidx];
+      pc = prm.pix[2 * pidx + 1];
+    }
+    const bool use = rok && flag == 0;
+    const EC bsk = use ? cto<EC>(prm.b_s[tk]) : czero<EC>();
+    EC gk = bsk;
+    if (r_b > 0) {
+#pragma unroll
+      for (int c = 0; c < RBM; ++c) {
+        if (c >= r_b) continue;
+        const EC coef = gsum<QP>(ccfma(vb[c], bsk, czero<EC>()));
+        if (use) gk = csub(gk, cmul(vb[c], coef));
+      }
+    }
+    const float2* xt = prm.x + (int64_t(pr) * W + pc) * Q;
+    EC w[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const EC xv = use ? cto<EC>(xt[int64_t(i) * H * W * Q + tk]) : czero<EC>();
+      w[i] = gsum<QP>(cmul(xv, cconj(gk)));
+    }
+    const ES den = gsum<QP>(ES(bsk.x * gk.x + bsk.y * gk.y));
+    const EC* Uq = sQUA[slot_ok ? tg : 0];   // U_A of the queued pixel, p x RAM
+    EC z[P];
+    {
+      EC cw[RAM];
+#pragma unroll
+      for (int c = 0; c < RAM; ++c) {
+        cw[c] = czero<EC>();
+        if (c < r_a) {
+#pragma unroll
+          for (int i = 0; i < P; ++i) cw[c] = ccfma(Uq[i * RAM + c], w[i], cw[c]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        z[i] = w[i];
+#pragma unroll
+        for (int c = 0; c < RAM; ++c)
+          if (c < r_a) z[i] = csub(z[i], cmul(Uq[i * RAM + c], cw[c]));
+      }
+    }
+    const bool den_ok = den > ES(1e-12) * ES(prm.bs_norm2);
+    float T;
+    if (prm.stat_mode == 0) {
+      ES num = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) num += cabs2(z[i]);
+      T = den_ok ? float(num / den) : 0.f;
+    } else {
+      EC hz = czero<EC>(), fh[P], hs[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) fh[i] = hs[i] = cto<EC>(prm.h_s[i]);
+#pragma unroll
+      for (int c = 0; c < RAM; ++c) {
+        if (c >= r_a) continue;
+        EC ch = czero<EC>();
+#pragma unroll
+        for (int i = 0; i < P; ++i) ch = ccfma(Uq[i * RAM + c], hs[i], ch);
+#pragma unroll
+        for (int i = 0; i < P; ++i) fh[i] = csub(fh[i], cmul(Uq[i * RAM + c], ch));
+      }
+      ES hfh = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        hz = ccfma(hs[i], z[i], hz);
+        hfh += hs[i].x * fh[i].x + hs[i].y * fh[i].y;
+      }
+      const bool ok = den_ok && hfh > ES(1e-12) * ES(prm.h_norm2);
+      T = ok ? float(cabs2(hz) / (hfh * den)) : 0.f;
+    }
+    if (!isfinite(T)) T = NAN;
+    if (flag == 1) T = 0.f;
+    if (flag == 2) T = NAN;
+    if (slot_ok && tk == 0) {
+      prm.T[pidx] = T;
+      if (MODE == kModeRun && prm.D) prm.D[pidx] = (T > prm.tau) ? 1 : 0;
+      if (MODE == kModeProbe) {
+        if (prm.eta) prm.eta[pidx] = sQeta[tg];
+        if (prm.iters) prm.iters[pidx] = sQit[tg];
+      }
+    }
+    if (MODE == kModeProbe && slot_ok) {
+      if (prm.UA && tk < P) {
+#pragma unroll
+        for (int c = 0; c < RAM; ++c)
+          if (c < r_a) prm.UA[(pidx * P + tk) * r_a + c] = (flag != 0) ? cz() : tof(sQUA[tg][tk * RAM + c]);
+      }
+      if (prm.UB && tk < Q) {
+#pragma unroll
+        for (int c = 0; c < RBM; ++c)
+          if (c < r_b) prm.UB[(pidx * Q + tk) * r_b + c] = (flag != 0) ? cz() : tof(vb[c]);
+      }
+    }
+    wave_sync();
+  };
+
+  for (int64_t it = 0; it < count; ++it) {
+    const int64_t idx = first + it;
+    int r, c;
+    if (MODE == kModeRun) {
+      r = int(idx / W);
+      c = int(idx - int64_t(r) * W);
+    } else {
+      r = prm.pix[2 * idx];
+      c = prm.pix[2 * idx + 1];
+    }
+    const bool valid = r >= prm.r0 && r < prm.r1 && c >= prm.c0 && c < prm.c1;
+    if (!valid) {
+      if (lane == 0) {
+        prm.T[idx] = 0.f;
+        if (MODE == kModeRun && prm.D) prm.D[idx] = 0;
+        if (MODE == kModeProbe) {
+          if (prm.eta) prm.eta[idx] = 0.f;
+          if (prm.iters) prm.iters[idx] = 0;
+        }
+      }
+      if (MODE == kModeProbe) {
+        if (prm.UA)
+          for (int e = lane; e < P * r_a; e += 64) prm.UA[idx * P * r_a + e] = cz();
+        if (prm.UB)
+          for (int e = lane; e < Q * r_b; e += 64) prm.UB[idx * Q * r_b + e] = cz();
+      }
+      continue;
+    }
+    const float2* xp = prm.x + (int64_t(r) * W + c) * Q;
+
+    // ---------------------------------------------------------------- a2 SCM
+    if constexpr (PREC == 0)
+      scm_fp32<P, Q>(xp, sOff, chan_off, row_ok, n, sS);
+    else
+      scm_bf16x3<P, Q>(xp, sOff, chan_off, row_ok, n, sS);
+
     // ------------------------------------------------ a4 init, ||R||_F = ||S||_F
     float2 A[P * P];
     double normR2;
@@ -441,20 +844,16 @@ __global__ __launch_bounds__(64) void kstap_fp32_kernel(const KParams prm) {
       for (int e = 0; e < P * P; ++e) A[e] = fallback ? wsum(pt[e]) : a0[e];
     }
 
-    float T = 0.f, eta = 0.f;
+    float eta = 0.f;
     int iters = 0;
     const bool zero = !(normR2 > 0.0);
     const bool bad = !isfinite(normR2);
-    float2 va[RAM];
-    float2 vb[RBM];
+    float2 bv[NE];
 #pragma unroll
-    for (int c = 0; c < RAM; ++c) va[c] = cz();
-#pragma unroll
-    for (int c = 0; c < RBM; ++c) vb[c] = cz();
+    for (int t = 0; t < NE; ++t) bv[t] = cz();
 
     if (!zero && !bad) {
       // --------------------------------------------------------- a5 LR-Kron
-      float2 bv[NE];
       float2 Ap[P * P];
       float bn2;
       double resid = 0.0;
@@ -507,41 +906,76 @@ __global__ __launch_bounds__(64) void kstap_fp32_kernel(const KParams prm) {
       };
 
       // EIG_{r_a}: A <- U (U^H A' U) U^H with U the top-r_a subspace of Herm(A')
+      EC ua[P];
+      EC va[RAM];
+#pragma unroll
+      for (int i = 0; i < P; ++i) ua[i] = czero<EC>();
+#pragma unroll
+      for (int c = 0; c < RAM; ++c) va[c] = czero<EC>();
       auto eig_a = [&](bool cold) {
-        if (lane == 0) {
+        EC Ah[P * P];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+          for (int j = 0; j < P; ++j)
+            Ah[i * P + j] = cscale(cadd(cto<EC>(Ap[i * P + j]), cconj(cto<EC>(Ap[j * P + i]))), ES(0.5));
+        if (r_a == 1) {
+          power_top<P, EC>(Ah, ua, cold, 500, PREC ? 1e-12 : 2e-6);
+          ES lam = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            EC s = czero<EC>();
+#pragma unroll
+            for (int j = 0; j < P; ++j) s = cfma(Ah[i * P + j], ua[j], s);
+            lam += ua[i].x * s.x + ua[i].y * s.y;
+          }
+          anorm2 = 0.f;
 #pragma unroll
           for (int i = 0; i < P; ++i)
 #pragma unroll
-            for (int j = 0; j < P; ++j)
-              sA[i * P + j] = cscale(cadd(Ap[i * P + j], cconj(Ap[j * P + i])), 0.5f);
+            for (int j = 0; j < P; ++j) {
+              A[i * P + j] = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
+              anorm2 += cabs2(A[i * P + j]);
+            }
+          if (lane < P) {
+            EC s = czero<EC>();
+#pragma unroll
+            for (int i = 0; i < P; ++i) s = (i == lane) ? ua[i] : s;
+            sUA[lane * RAM] = s;
+          }
+          wave_sync();
+          return;
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int e = 0; e < P * P; ++e) {
+            sA[e] = tof(Ah[e]);
+            sAh[e] = Ah[e];
+          }
         }
         wave_sync();
-        top_subspace<RAM>(sA, P, r_a, va, sVa, cold, 200, 2e-6f, 1);
+        float2 mrow[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) mrow[j] = sA[(lane < P ? lane : 0) * P + j];
+        group_subspace<RAM, 64, P, EC>(mrow, lane < P, r_a, va, sVa, cold, 500, PREC ? 1e-12 : 2e-6);
         if (lane < P) {
 #pragma unroll
           for (int c = 0; c < RAM; ++c)
             if (c < r_a) sUA[lane * RAM + c] = va[c];
         }
         wave_sync();
-        float2 U[P][RAM];
-#pragma unroll
-        for (int i = 0; i < P; ++i)
-#pragma unroll
-          for (int c = 0; c < RAM; ++c) U[i][c] = (c < r_a) ? sUA[i * RAM + c] : cz();
-        // Hs = U^H Herm(A') U
-        float2 Hs[RAM][RAM];
+        // Hs = U^H Herm(A') U and A = U Hs U^H, reading U and Herm(A') from LDS
+        EC Hs[RAM][RAM];
 #pragma unroll
         for (int a = 0; a < RAM; ++a)
 #pragma unroll
           for (int b = 0; b < RAM; ++b) {
-            float2 s = cz();
+            EC s = czero<EC>();
             if (a < r_a && b < r_a) {
-#pragma unroll
               for (int i = 0; i < P; ++i) {
-                float2 t2 = cz();
-#pragma unroll
-                for (int j = 0; j < P; ++j) t2 = cfma(sA[i * P + j], U[j][b], t2);
-                s = ccfma(U[i][a], t2, s);
+                EC t2 = czero<EC>();
+                for (int j = 0; j < P; ++j) t2 = cfma(sAh[i * P + j], sUA[j * RAM + b], t2);
+                s = ccfma(sUA[i * RAM + a], t2, s);
               }
             }
             Hs[a][b] = s;
@@ -551,14 +985,18 @@ __global__ __launch_bounds__(64) void kstap_fp32_kernel(const KParams prm) {
         for (int i = 0; i < P; ++i)
 #pragma unroll
           for (int j = 0; j < P; ++j) {
-            float2 s = cz();
+            EC s = czero<EC>();
 #pragma unroll
-            for (int a = 0; a < RAM; ++a)
+            for (int a = 0; a < RAM; ++a) {
+              if (a >= r_a) continue;
+              EC t2 = czero<EC>();
 #pragma unroll
               for (int b = 0; b < RAM; ++b)
-                if (a < r_a && b < r_a) s = cfma(cmul(U[i][a], Hs[a][b]), cconj(U[j][b]), s);
-            A[i * P + j] = s;
-            anorm2 += cabs2(s);
+                if (b < r_a) t2 = cfma(Hs[a][b], cconj(sUA[j * RAM + b]), t2);
+              s = cfma(sUA[i * RAM + a], t2, s);
+            }
+            A[i * P + j] = tof(s);
+            anorm2 += cabs2(A[i * P + j]);
           }
         wave_sync();
       };
@@ -579,181 +1017,79 @@ __global__ __launch_bounds__(64) void kstap_fp32_kernel(const KParams prm) {
         ++iters;
       }
       // bv now holds the final b = R^T conj(a) / ||a||^2
-
-      // --------------------------------------------- a6 temporal subspace
-      wave_sync();   // S is dead from here on
-      float2* sB = sS;          // raw B, row-major q x q (B[k][l] = b[k + q l] in vec form)
-      float2* sBh = sS + QQ;    // Hermitian part
-      float2* sVb = sS + 2 * QQ;
-#pragma unroll
-      for (int t = 0; t < NE; ++t) {
-        const int e = lane + 64 * t;
-        if (e < QQ) sB[e] = bv[t];
-      }
-      wave_sync();
-#pragma unroll
-      for (int t = 0; t < NE; ++t) {
-        const int e = lane + 64 * t;
-        if (e < QQ) {
-          const int k = e / Q, l = e - (e / Q) * Q;
-          sBh[e] = cscale(cadd(sB[k * Q + l], cconj(sB[l * Q + k])), 0.5f);
-        }
-      }
-      wave_sync();
-      if (r_b > 0) top_subspace<RBM>(sBh, Q, r_b, vb, sVb, true, 200, 2e-6f, 1);
-
-      // ------------------------------------------------------ a8 statistic
-      const int k = lane;
-      const bool kq = k < Q;
-      const float2 bsk = kq ? prm.b_s[k] : cz();
-      float2 g = bsk;
-      if (r_b > 0) {
-        float2 coef[RBM];
-#pragma unroll
-        for (int c = 0; c < RBM; ++c)
-          if (c < r_b) coef[c] = wsum(kq ? ccfma(vb[c], bsk, cz()) : cz());
-        if (kq) {
-#pragma unroll
-          for (int c = 0; c < RBM; ++c)
-            if (c < r_b) g = csub(g, cmul(vb[c], coef[c]));
-        }
-      }
-      float2 w[P];
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const float2 xv = kq ? xp[int64_t(i) * H * W * Q + k] : cz();
-        w[i] = wsum(kq ? cmul(xv, cconj(g)) : cz());
-      }
-      const float den = wsum(kq ? fmaf(bsk.x, g.x, bsk.y * g.y) : 0.f);
-      // z = F_A w with U_A from the last EIG (sUA)
-      float2 U[P][RAM];
-#pragma unroll
-      for (int i = 0; i < P; ++i)
-#pragma unroll
-        for (int c = 0; c < RAM; ++c) U[i][c] = (c < r_a) ? sUA[i * RAM + c] : cz();
-      float2 z[P];
-      {
-        float2 cw[RAM];
-#pragma unroll
-        for (int c = 0; c < RAM; ++c) {
-          cw[c] = cz();
-          if (c < r_a) {
-#pragma unroll
-            for (int i = 0; i < P; ++i) cw[c] = ccfma(U[i][c], w[i], cw[c]);
-          }
-        }
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-          z[i] = w[i];
-#pragma unroll
-          for (int c = 0; c < RAM; ++c)
-            if (c < r_a) z[i] = csub(z[i], cmul(U[i][c], cw[c]));
-        }
-      }
-      const bool den_ok = den > 1e-12f * prm.bs_norm2;
-      if (prm.stat_mode == 0) {
-        float num = 0.f;
-#pragma unroll
-        for (int i = 0; i < P; ++i) num += cabs2(z[i]);
-        T = den_ok ? num / den : 0.f;
-      } else {
-        float2 hz = cz(), fh[P];
-#pragma unroll
-        for (int i = 0; i < P; ++i) fh[i] = prm.h_s[i];
-#pragma unroll
-        for (int c = 0; c < RAM; ++c) {
-          if (c >= r_a) continue;
-          float2 ch = cz();
-#pragma unroll
-          for (int i = 0; i < P; ++i) ch = ccfma(U[i][c], prm.h_s[i], ch);
-#pragma unroll
-          for (int i = 0; i < P; ++i) fh[i] = csub(fh[i], cmul(U[i][c], ch));
-        }
-        float hfh = 0.f;
-#pragma unroll
-        for (int i = 0; i < P; ++i) {
-          hz = ccfma(prm.h_s[i], z[i], hz);
-          hfh += fmaf(prm.h_s[i].x, fh[i].x, prm.h_s[i].y * fh[i].y);
-        }
-        const bool ok = den_ok && hfh > 1e-12f * prm.h_norm2;
-        T = ok ? cabs2(hz) / (hfh * den) : 0.f;
-      }
-      if (!isfinite(T)) T = NAN;
-    } else if (bad) {
-      T = NAN;
     }
 
-    if (lane == 0) {
-      prm.T[out_idx] = T;
-      if (MODE == kModeRun && prm.D) prm.D[out_idx] = (T > prm.tau) ? 1 : 0;
-      if (MODE == kModeProbe) {
-        if (prm.eta) prm.eta[idx] = eta;
-        if (prm.iters) prm.iters[idx] = iters;
-      }
-    }
-    if (MODE == kModeProbe) {
-      if (prm.UA && lane < P) {
+    // ------------------------------------------ enqueue for the batched tail
+    wave_sync();   // S is dead from here on
 #pragma unroll
-        for (int c = 0; c < RAM; ++c)
-          if (c < r_a) prm.UA[(idx * P + lane) * r_a + c] = (zero || bad) ? cz() : sUA[lane * RAM + c];
-      }
-      if (prm.UB && lane < Q) {
-#pragma unroll
-        for (int c = 0; c < RBM; ++c)
-          if (c < r_b) prm.UB[(idx * Q + lane) * r_b + c] = (zero || bad) ? cz() : vb[c];
-      }
+    for (int t = 0; t < NE; ++t) {
+      const int e = lane + 64 * t;
+      if (e < QQ) sS[e] = bv[t];   // B[k][l] at k*q + l
     }
     wave_sync();
+    if (tg == nq && tk < Q) {
+#pragma unroll
+      for (int l = 0; l < Q; ++l) Bq[l] = cscale(cadd(sS[tk * Q + l], cconj(sS[l * Q + tk])), 0.5f);
+    }
+    if (lane == 0) {
+      sQidx[nq] = idx;
+      sQflag[nq] = bad ? 2 : (zero ? 1 : 0);
+      sQeta[nq] = eta;
+      sQit[nq] = iters;
+    }
+    if (lane < P * RAM) sQUA[nq][lane] = (zero || bad) ? czero<EC>() : sUA[lane];
+    wave_sync();
+    if (++nq == G) {
+      tail(G);
+      nq = 0;
+    }
   }
+  if (nq > 0) tail(nq);
 }
 
 // ---------------------------------------------------------------- dispatch
-typedef void (*KernelFn)(const KParams);
-
-template <int P, int Q, int RBM>
+template <int P, int Q, int RBM, int PREC>
 int launch_one(int mode, const KParams& prm, hipStream_t stream) {
   int64_t units = (mode == kModeRun) ? int64_t(prm.nlogical) : (int64_t(prm.npix) + prm.pix_per_block - 1) / prm.pix_per_block;
   if (units <= 0) return hipSuccess;
   int64_t grid = (mode == kModeRun) ? ((units + 7) / 8) * 8 : units;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
   if (mode == kModeRun)
-    hipLaunchKernelGGL((kstap_fp32_kernel<P, Q, RBM, kModeRun>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
+    hipLaunchKernelGGL((kstap_kernel<P, Q, RBM, kModeRun, PREC>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
   else
-    hipLaunchKernelGGL((kstap_fp32_kernel<P, Q, RBM, kModeProbe>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
+    hipLaunchKernelGGL((kstap_kernel<P, Q, RBM, kModeProbe, PREC>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
   return hipGetLastError();
 }
 
 struct Entry {
-  int p, q, rbm;
+  int p, q, rbm, prec;
   int (*fn)(int, const KParams&, hipStream_t);
 };
 
-#define KSTAP_ENTRY(P, Q, R) {P, Q, R, &launch_one<P, Q, R>}
+#define KSTAP_ENTRY(P, Q, R, X) {P, Q, R, X, &launch_one<P, Q, R, X>}
 const Entry kTable[] = {
-    KSTAP_ENTRY(2, 8, 4),  KSTAP_ENTRY(2, 16, 4), KSTAP_ENTRY(2, 32, 4),
-    KSTAP_ENTRY(3, 8, 4),  KSTAP_ENTRY(3, 8, 8),  KSTAP_ENTRY(3, 12, 4), KSTAP_ENTRY(3, 12, 8),
-    KSTAP_ENTRY(3, 16, 4), KSTAP_ENTRY(3, 16, 8), KSTAP_ENTRY(4, 8, 4),  KSTAP_ENTRY(4, 16, 4),
-    KSTAP_ENTRY(6, 8, 4),
+    KSTAP_ENTRY(2, 8, 4, 0),  KSTAP_ENTRY(2, 16, 4, 0), KSTAP_ENTRY(2, 32, 4, 0),
+    KSTAP_ENTRY(3, 8, 4, 0),  KSTAP_ENTRY(3, 8, 8, 0),  KSTAP_ENTRY(3, 12, 4, 0), KSTAP_ENTRY(3, 12, 8, 0),
+    KSTAP_ENTRY(3, 16, 4, 0), KSTAP_ENTRY(3, 16, 8, 0), KSTAP_ENTRY(4, 8, 4, 0),  KSTAP_ENTRY(4, 16, 4, 0),
+    KSTAP_ENTRY(6, 8, 4, 0),
+    KSTAP_ENTRY(3, 8, 4, 1),  KSTAP_ENTRY(3, 8, 8, 1),  KSTAP_ENTRY(3, 12, 4, 1), KSTAP_ENTRY(3, 12, 8, 1),
+    KSTAP_ENTRY(3, 16, 4, 1), KSTAP_ENTRY(3, 16, 8, 1),
 };
 #undef KSTAP_ENTRY
 
-const Entry* find(int p, int q, int r_b) {
+const Entry* find(int p, int q, int r_b, int prec) {
   const int rbm = (r_b <= 4) ? 4 : 8;
   for (const Entry& e : kTable)
-    if (e.p == p && e.q == q && e.rbm == rbm) return &e;
+    if (e.p == p && e.q == q && e.rbm == rbm && e.prec == prec) return &e;
   return nullptr;
 }
 
 }  // namespace
 
-bool kernel_available(int p, int q, int r_b, int precision) {
-  if (precision != 0) return false;
-  return find(p, q, r_b) != nullptr;
-}
+bool kernel_available(int p, int q, int r_b, int precision) { return find(p, q, r_b, precision) != nullptr; }
 
 int launch_pixels(int p, int q, int precision, int mode, const KParams& prm, hipStream_t stream) {
-  if (precision != 0) return hipErrorInvalidValue;
-  const Entry* e = find(p, q, prm.r_b);
+  const Entry* e = find(p, q, prm.r_b, precision);
   if (!e) return hipErrorInvalidValue;
   return e->fn(mode, prm, stream);
 }
