@@ -155,11 +155,20 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
                        const int32_t* pix, int32_t npix, const stap_probe_out* out,
                        void* hip_stream);
 
-/* Batched uneven tiles: runs every tile (each with its own plan, frame, size
- * and outputs) in one persistent launch ordered longest-first.  Results are
- * identical to stap_run on each tile alone.  `tiles` is a host array.  The
- * call copies the tile table to the device and waits for that copy before
- * returning; the compute itself is only enqueued.
+/* Batched uneven tiles (tiles may differ in p, q, n, ranks, steering,
+ * precision and size; each has its own plan, frame and outputs).
+ *
+ * stap_batch_create validates every tile, uploads a tile table to device
+ * memory it owns, numbers the work items (runs of `pix_per_item` consecutive
+ * pixels of one tile) longest tile first within each kernel class, and
+ * builds one HIP graph: a counter-reset kernel node followed, as parallel
+ * branches, by one persistent kernel node per kernel class present; every
+ * workgroup of a persistent kernel pops work items from a device counter until
+ * the queue is empty.  pix_per_item = 0 takes the autotuned value cached for
+ * this batch signature in this process, else 16.  Results are bitwise equal to
+ * stap_run on each tile alone.  The frames and outputs named by the tiles must
+ * stay valid while the batch is launched.  Must be called with the device that
+ * will run the batch current.
  * Errors: INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
 typedef struct {
   const stap_plan_t* plan;
@@ -169,7 +178,76 @@ typedef struct {
   uint8_t* D;
 } stap_tile;
 
+typedef struct stap_batch_s stap_batch_t;
+
+stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pix_per_item, stap_batch_t** out);
+
+/* One hipGraphLaunch of the captured graph on hip_stream (asynchronous). */
+stap_status stap_batch_launch(stap_batch_t* batch, void* hip_stream);
+
+/* Autotuner: times the batch (synchronously, on hip_stream, with direct
+ * launches) for work-item sizes {4, 8, 16, 32} pixels and persistent grids of
+ * {1, 2} x (compute units x 8) workgroups, keeps the fastest (rebuilds the
+ * graph once), and records it
+ * for this batch signature (kernel classes present and total pixels) in a
+ * process-wide cache.  best_ppb / best_grid_mult / best_ms may be NULL. */
+stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best_ppb, int32_t* best_grid_mult,
+                            double* best_ms);
+
+/* Batch facts: total pixels, kernel classes present, work-item size, grid
+ * multiplier.  Any output pointer may be NULL. */
+stap_status stap_batch_info(const stap_batch_t* batch, int64_t* pixels, int32_t* classes, int32_t* pix_per_item,
+                            int32_t* grid_mult);
+
+/* Frees the batch and its device memory; waits for nothing (launched work
+ * must have completed).  NULL is accepted. */
+stap_status stap_batch_destroy(stap_batch_t* batch);
+
+/* One-shot form: create, launch on hip_stream, synchronise hip_stream,
+ * destroy. */
 stap_status stap_run_batch(const stap_tile* tiles, int32_t ntiles, void* hip_stream);
+
+/* Serving with continuous batching.
+ *
+ * A server owns an HBM arena of hbm_budget_bytes (allocated on the current
+ * device at creation), a copy stream, a compute stream and a worker thread.
+ * Frames are admitted in arrival order as soon as their device buffers
+ * (input unless x_on_device, T, D) fit in the arena and fewer than
+ * max_inflight frames are active; their host-to-device copies overlap the
+ * running computation.  Each scheduling step processes a fair-share slice of
+ * every active frame, about step_pixels pixels in total (0 = 2^20), in one
+ * persistent launch per kernel class, so frames that arrive while others are
+ * on the GPU join at the next step.  Results are bitwise equal to stap_run on
+ * the frame alone.  Host frames in pinned memory give asynchronous copies.
+ * Errors of create: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+typedef struct stap_server_s stap_server_t;
+
+stap_status stap_server_create(size_t hbm_budget_bytes, int32_t max_inflight, int64_t step_pixels,
+                               stap_server_t** out);
+
+/* Queues one frame.  x: complex64 [p][H][W][q], host memory (or device memory
+ * if x_on_device != 0); T_host: float [H][W] and D_host: uint8 [H][W] (or
+ * NULL), host memory written when the frame completes.  x, T_host and D_host
+ * must stay valid until stap_server_wait returns for the ticket.  Returns at
+ * once with a ticket.  Errors: INVALID_ARG, UNSUPPORTED, BUSY (the frame can
+ * never fit in the budget), DEVICE. */
+stap_status stap_server_submit(stap_server_t* server, const stap_plan_t* plan, const void* x, int32_t H, int32_t W,
+                               int32_t x_on_device, float* T_host, uint8_t* D_host, uint64_t* ticket);
+
+/* Waits until the frame's results are in T_host / D_host (timeout_ms < 0:
+ * no limit) and releases the ticket.  latency_s: submit to results in host
+ * memory.  Errors: INVALID_ARG (unknown ticket), BUSY (timed out; the ticket
+ * stays valid), DEVICE (the frame failed). */
+stap_status stap_server_wait(stap_server_t* server, uint64_t ticket, int32_t timeout_ms, double* latency_s);
+
+/* Latency percentiles of the frames completed so far, and completed pixels
+ * per second between the first submission and the last completion. */
+stap_status stap_server_stats(stap_server_t* server, double* p50_s, double* p99_s, double* pixels_per_s,
+                              int64_t* frames_done);
+
+/* Finishes every queued frame, then frees the server.  Tickets not yet waited
+ * for are released.  NULL is accepted. */
+stap_status stap_server_destroy(stap_server_t* server);
 
 /* Library version string and the HIP device architecture the code object
  * was built for. */

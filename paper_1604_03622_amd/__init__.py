@@ -78,6 +78,18 @@ def lib() -> ctypes.CDLL:
         "stap_run": [p_, p_, i32, i32, p_, p_, p_],
         "stap_probe": [p_, p_, i32, i32, p_, i32, ctypes.POINTER(StapProbeOut), p_],
         "stap_run_batch": [ctypes.POINTER(StapTile), i32, p_],
+        "stap_batch_create": [ctypes.POINTER(StapTile), i32, i32, ctypes.POINTER(p_)],
+        "stap_batch_launch": [p_, p_],
+        "stap_batch_tune": [p_, p_, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
+        "stap_batch_info": [p_, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                            ctypes.POINTER(i32)],
+        "stap_batch_destroy": [p_],
+        "stap_server_create": [ctypes.c_size_t, i32, ctypes.c_int64, ctypes.POINTER(p_)],
+        "stap_server_submit": [p_, p_, p_, i32, i32, i32, p_, p_, ctypes.POINTER(ctypes.c_uint64)],
+        "stap_server_wait": [p_, ctypes.c_uint64, i32, ctypes.POINTER(ctypes.c_double)],
+        "stap_server_stats": [p_, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+        "stap_server_destroy": [p_],
     }
     for name, args in sigs.items():
         fn = getattr(L, name)
@@ -219,14 +231,109 @@ def probe(plan: Plan, x, pix, stream=None) -> dict:
     return out
 
 
-def run_batch(tiles, stream=None):
-    """tiles: list of (plan, x, T, D) with torch tensors; runs them in one call."""
+def _tile_array(tiles):
     arr = (StapTile * len(tiles))()
     for i, (plan, x, T, D) in enumerate(tiles):
         H, W = _check_frame(plan, x)
         arr[i] = StapTile(plan.handle.value, x.data_ptr(), H, W, T.data_ptr(),
                           D.data_ptr() if D is not None else None)
-    _check(lib().stap_run_batch(arr, len(tiles), _stream_handle(stream)))
+    return arr
+
+
+def run_batch(tiles, stream=None):
+    """tiles: list of (plan, x, T, D) with torch tensors; one-shot batched run
+    (creates, launches, synchronises and frees a Batch)."""
+    _check(lib().stap_run_batch(_tile_array(tiles), len(tiles), _stream_handle(stream)))
+
+
+class Batch:
+    """Reusable batch of uneven tiles captured in one HIP graph (see
+    stap_batch_create).  Keeps references to the tiles' tensors."""
+
+    def __init__(self, tiles, pix_per_item: int = 0):
+        self._tiles = list(tiles)
+        self._arr = _tile_array(self._tiles)
+        h = ctypes.c_void_p()
+        _check(lib().stap_batch_create(self._arr, len(self._tiles), pix_per_item, ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().stap_batch_launch(self._h, _stream_handle(stream)))
+
+    def tune(self, stream=None):
+        ppb, mult, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().stap_batch_tune(self._h, _stream_handle(stream), ctypes.byref(ppb), ctypes.byref(mult),
+                                     ctypes.byref(ms)))
+        return dict(pix_per_item=ppb.value, grid_mult=mult.value, ms=ms.value)
+
+    def info(self):
+        px, cl, ppb, mult = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().stap_batch_info(self._h, ctypes.byref(px), ctypes.byref(cl), ctypes.byref(ppb),
+                                     ctypes.byref(mult)))
+        return dict(pixels=px.value, classes=cl.value, pix_per_item=ppb.value, grid_mult=mult.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.stap_batch_destroy(h)
+            self._h = None
+
+
+class Server:
+    """Continuous-batching server (see stap_server_create).  Frames are host
+    numpy/torch-CPU complex64 arrays [p, H, W, q] (pinned torch tensors give
+    asynchronous copies) or device torch tensors."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 16, step_pixels: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().stap_server_create(int(hbm_budget_bytes), int(max_inflight), int(step_pixels),
+                                        ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, plan: Plan, x, with_detections: bool = True) -> int:
+        import torch
+        if isinstance(x, np.ndarray):
+            x = torch.from_numpy(np.ascontiguousarray(x))
+        if x.dtype != torch.complex64 or x.dim() != 4 or x.shape[0] != plan.p or x.shape[3] != plan.q:
+            raise ValueError("x must be complex64 [p, H, W, q]")
+        x = x.contiguous()
+        H, W = int(x.shape[1]), int(x.shape[2])
+        T = torch.empty((H, W), dtype=torch.float32, pin_memory=True)
+        D = torch.empty((H, W), dtype=torch.uint8, pin_memory=True) if with_detections else None
+        t = ctypes.c_uint64()
+        _check(lib().stap_server_submit(self._h, plan.handle, ctypes.c_void_p(x.data_ptr()), H, W, int(x.is_cuda),
+                                        ctypes.c_void_p(T.data_ptr()),
+                                        ctypes.c_void_p(D.data_ptr()) if D is not None else None, ctypes.byref(t)))
+        self._keep[t.value] = (plan, x, T, D)
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        lat = ctypes.c_double()
+        try:
+            _check(lib().stap_server_wait(self._h, ticket, timeout_ms, ctypes.byref(lat)))
+        except StapError as e:
+            if e.status != 5:
+                self._keep.pop(ticket, None)
+            raise
+        plan, x, T, D = self._keep.pop(ticket)
+        return T, D, lat.value
+
+    def stats(self):
+        p50, p99, pps, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().stap_server_stats(self._h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(pps),
+                                       ctypes.byref(n)))
+        return dict(p50_s=p50.value, p99_s=p99.value, pixels_per_s=pps.value, frames=n.value)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.stap_server_destroy(h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()
 
 
 def version() -> str:

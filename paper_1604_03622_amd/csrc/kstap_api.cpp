@@ -1,7 +1,5 @@
 // Host runtime and C ABI of the Kron-STAP library: configuration checks,
 // training stencil, CFAR threshold, launch set-up.  See include/kstap.h.
-#include "../../include/kstap.h"
-
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -10,6 +8,8 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <map>
+#include <mutex>
 #include <set>
 #include <string>
 #include <utility>
@@ -17,137 +17,152 @@
 
 #include "kstap_internal.h"
 
-struct stap_plan_s {
-  stap_config cfg;                 // copy; the pointer members point into the vectors below
-  std::vector<int32_t> stencil;    // n (dr, dc) pairs
-  std::vector<float> b_steer;      // 2q
-  std::vector<float> h_steer;      // 2p (fixed mode)
-  double tau = 0.0;
-  int32_t window = 0;
-  int32_t dr_min = 0, dr_max = 0, dc_min = 0, dc_max = 0;
+#include "kstap_host.h"
+
+using namespace kstap::host;
+
+namespace {
+
+// ------------------------------------------------------------------ batches
+struct BatchClass {
+  int cls = -1;                  // kernel class
+  std::vector<int32_t> order;    // tiles of this class, longest first
+};
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+  return cus;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune_cache;   // signature -> (ppb, grid multiplier)
+
+}  // namespace
+
+struct stap_batch_s {
+  std::vector<kstap::KParams> descs;
+  std::vector<BatchClass> classes;
+  int64_t pixels = 0;
+  int ppb = 16;
+  int grid_mult = 1;
+  std::string signature;
+  // device
+  void* d_buf = nullptr;         // descs | order | prefix | counters
+  kstap::KParams* d_descs = nullptr;
+  int32_t* d_order = nullptr;
+  int64_t* d_prefix = nullptr;
+  unsigned long long* d_counters = nullptr;
+  std::vector<size_t> order_base, prefix_base;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
 };
 
 namespace {
 
-thread_local std::string g_last_error;
-
-stap_status fail(stap_status st, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  g_last_error = buf;
-  return st;
+void batch_release_graph(stap_batch_s* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
 }
 
-stap_status ok() {
-  g_last_error.clear();
+// Numbers the work items for the current ppb and uploads the prefix tables.
+stap_status batch_tables(stap_batch_s* b) {
+  std::vector<int64_t> prefix;
+  b->prefix_base.clear();
+  for (const BatchClass& c : b->classes) {
+    b->prefix_base.push_back(prefix.size());
+    int64_t acc = 0;
+    for (int32_t t : c.order) {
+      prefix.push_back(acc);
+      const int64_t px = b->descs[t].range_end - b->descs[t].range_first;
+      acc += (px + b->ppb - 1) / b->ppb;
+    }
+    prefix.push_back(acc);
+  }
+  hipError_t e = hipMemcpy(b->d_prefix, prefix.data(), prefix.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "prefix upload: %s", hipGetErrorString(e));
   return STAP_OK;
 }
 
-// P(Gamma(k, 1) > t) = exp(-t) * sum_{i<k} t^i / i!  for integer k >= 1.
-double gamma_sf_int(int k, double t) {
-  double term = 1.0, sum = 1.0;
-  for (int i = 1; i < k; ++i) {
-    term *= t / i;
-    sum += term;
+// Builds the graph explicitly (no stream capture): a counter-reset kernel
+// node, then one persistent kernel node per class, all depending only on the
+// reset node (parallel branches).
+stap_status batch_build(stap_batch_s* b) {
+  batch_release_graph(b);
+  stap_status st = batch_tables(b);
+  if (st != STAP_OK) return st;
+  const int grid = device_cus() * 8 * b->grid_mult;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "graph create: %s", hipGetErrorString(e));
+  unsigned long long* ctr = b->d_counters;
+  int ncls = int(b->classes.size());
+  void* reset_args[] = {&ctr, &ncls};
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.func = const_cast<void*>(kstap::reset_kernel());
+  kp.gridDim = dim3(1);
+  kp.blockDim = dim3(64);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = reset_args;
+  kp.extra = nullptr;
+  hipGraphNode_t reset_node = nullptr;
+  e = hipGraphAddKernelNode(&reset_node, g, nullptr, 0, &kp);
+  for (size_t i = 0; i < b->classes.size() && e == hipSuccess; ++i) {
+    const BatchClass& c = b->classes[i];
+    const kstap::KParams* descs = b->d_descs;
+    const int32_t* order = b->d_order + b->order_base[i];
+    const int64_t* prefix = b->d_prefix + b->prefix_base[i];
+    int nt = int(c.order.size());
+    int ppb = b->ppb;
+    unsigned long long* counter = b->d_counters + i;
+    void* args[] = {&descs, &order, &prefix, &nt, &ppb, &counter};
+    hipKernelNodeParams np;
+    std::memset(&np, 0, sizeof(np));
+    np.func = const_cast<void*>(kstap::persistent_kernel(c.cls));
+    np.gridDim = dim3(grid);
+    np.blockDim = dim3(64);
+    np.sharedMemBytes = 0;
+    np.kernelParams = args;
+    np.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, g, &reset_node, 1, &np);
   }
-  return std::exp(-t) * sum;
-}
-
-// Upper-tail quantile of Gamma(k, 1): the threshold with false-alarm rate pfa
-// for a statistic whose null law (white noise, exact subspaces) is Gamma(k, 1).
-double gamma_isf_int(int k, double pfa) {
-  double lo = 0.0, hi = 1.0;
-  while (gamma_sf_int(k, hi) > pfa) hi *= 2.0;
-  for (int it = 0; it < 200 && hi - lo > 1e-15 * hi; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (gamma_sf_int(k, mid) > pfa)
-      lo = mid;
-    else
-      hi = mid;
+  if (e != hipSuccess) {
+    hipGraphDestroy(g);
+    return fail(STAP_ERR_DEVICE, "graph nodes: %s", hipGetErrorString(e));
   }
-  return 0.5 * (lo + hi);
-}
-
-// Default training stencil: window [-W/2, W/2-1]^2 minus the centred
-// guard x guard block, nearest offsets first (ties by dr, then dc).
-bool default_stencil(int n, int window, int guard, std::vector<int32_t>* out, int* w_used) {
-  int w = window;
-  if (w <= 0) {
-    w = 10;
-    while (w * w - guard * guard < n) w += 2;
+  b->graph = g;
+  e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    b->exec = nullptr;
+    return fail(STAP_ERR_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
   }
-  const int half = w / 2, g = guard / 2;
-  std::vector<std::pair<int, int>> cand;
-  for (int dr = -half; dr < w - half; ++dr)
-    for (int dc = -half; dc < w - half; ++dc)
-      if (!(std::abs(dr) <= g && std::abs(dc) <= g)) cand.emplace_back(dr, dc);
-  if (int(cand.size()) < n) return false;
-  std::stable_sort(cand.begin(), cand.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) {
-    const int da = a.first * a.first + a.second * a.second, db = b.first * b.first + b.second * b.second;
-    if (da != db) return da < db;
-    if (a.first != b.first) return a.first < b.first;
-    return a.second < b.second;
-  });
-  out->clear();
-  for (int m = 0; m < n; ++m) {
-    out->push_back(cand[m].first);
-    out->push_back(cand[m].second);
-  }
-  *w_used = w;
-  return true;
-}
-
-void valid_region(const stap_plan_s* pl, int H, int W, int* r0, int* r1, int* c0, int* c1) {
-  *r0 = std::max(0, -pl->dr_min);
-  *r1 = std::max(*r0, H - std::max(0, pl->dr_max));
-  *c0 = std::max(0, -pl->dc_min);
-  *c1 = std::max(*c0, W - std::max(0, pl->dc_max));
-}
-
-stap_status fill_params(const stap_plan_s* pl, const void* x, int H, int W, kstap::KParams* k) {
-  const stap_config& c = pl->cfg;
-  std::memset(k, 0, sizeof(*k));
-  k->x = static_cast<const float2*>(x);
-  k->H = H;
-  k->W = W;
-  k->n = c.n;
-  k->r_a = c.r_a;
-  k->r_b = c.r_b;
-  k->min_iter = c.min_iter;
-  k->max_iter = c.max_iter;
-  k->stat_mode = c.stat_mode;
-  k->eps = c.eps;
-  k->tau = float(pl->tau);
-  float bn = 0.f, hn = 0.f;
-  for (int j = 0; j < c.q; ++j) {
-    k->b_s[j] = make_float2(pl->b_steer[2 * j], pl->b_steer[2 * j + 1]);
-    bn += k->b_s[j].x * k->b_s[j].x + k->b_s[j].y * k->b_s[j].y;
-  }
-  for (int i = 0; i < c.p && !pl->h_steer.empty(); ++i) {
-    k->h_s[i] = make_float2(pl->h_steer[2 * i], pl->h_steer[2 * i + 1]);
-    hn += k->h_s[i].x * k->h_s[i].x + k->h_s[i].y * k->h_s[i].y;
-  }
-  k->bs_norm2 = bn;
-  k->h_norm2 = hn;
-  for (int m = 0; m < c.n; ++m) {
-    k->st[2 * m] = int16_t(pl->stencil[2 * m]);
-    k->st[2 * m + 1] = int16_t(pl->stencil[2 * m + 1]);
-  }
-  valid_region(pl, H, W, &k->r0, &k->r1, &k->c0, &k->c1);
   return STAP_OK;
 }
 
-stap_status check_frame(const stap_plan_s* pl, const void* x, int H, int W) {
-  if (!pl) return fail(STAP_ERR_INVALID_ARG, "plan is NULL");
-  if (!x) return fail(STAP_ERR_INVALID_ARG, "x is NULL");
-  if (H < 1 || W < 1) return fail(STAP_ERR_INVALID_ARG, "frame size %d x %d must be positive", H, W);
-  const int64_t elems = int64_t(pl->cfg.p) * H * W * pl->cfg.q;
-  if (elems >= (int64_t(1) << 31))
-    return fail(STAP_ERR_INVALID_ARG, "frame of %lld complex samples exceeds 2^31 - 1", (long long)elems);
+// The same work launched directly on `s` (used by the tuner, so that timing
+// candidates needs no graph).
+stap_status batch_launch_direct(stap_batch_s* b, hipStream_t s) {
+  const int grid = device_cus() * 8 * b->grid_mult;
+  int le = kstap::launch_reset(b->d_counters, int(b->classes.size()), s);
+  for (size_t i = 0; i < b->classes.size() && le == hipSuccess; ++i) {
+    const BatchClass& c = b->classes[i];
+    le = kstap::launch_persistent(c.cls, b->d_descs, b->d_order + b->order_base[i], b->d_prefix + b->prefix_base[i],
+                                  int(c.order.size()), b->ppb, b->d_counters + i, grid, s);
+  }
+  if (le != hipSuccess) return fail(STAP_ERR_DEVICE, "batch launch: %s", hipGetErrorString(hipError_t(le)));
   return STAP_OK;
+}
+
+void batch_free(stap_batch_s* b) {
+  if (!b) return;
+  batch_release_graph(b);
+  if (b->d_buf) hipFree(b->d_buf);
+  delete b;
 }
 
 }  // namespace
@@ -368,17 +383,209 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
   return ok();
 }
 
-stap_status stap_run_batch(const stap_tile* tiles, int32_t ntiles, void* hip_stream) {
-  if (ntiles < 0 || (ntiles > 0 && !tiles)) return fail(STAP_ERR_INVALID_ARG, "bad tile list");
+stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pix_per_item, stap_batch_t** out) {
+  if (!out) return fail(STAP_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (ntiles < 1 || !tiles) return fail(STAP_ERR_INVALID_ARG, "need at least one tile");
+  if (pix_per_item < 0 || pix_per_item > 4096) return fail(STAP_ERR_INVALID_ARG, "pix_per_item outside [0, 4096]");
+  stap_batch_s* b = new (std::nothrow) stap_batch_s();
+  if (!b) return fail(STAP_ERR_OUT_OF_MEMORY, "batch allocation failed");
+  std::map<int, int> cls_index;
+  std::vector<double> cost(ntiles);
   for (int t = 0; t < ntiles; ++t) {
-    stap_status st = stap_run(tiles[t].plan, tiles[t].x, tiles[t].H, tiles[t].W, tiles[t].T, tiles[t].D, hip_stream);
-    if (st != STAP_OK) return st;
+    const stap_tile& tl = tiles[t];
+    stap_status st = check_frame(tl.plan, tl.x, tl.H, tl.W);
+    if (st != STAP_OK) {
+      batch_free(b);
+      return fail(st, "tile %d: %s", t, last_error().c_str());
+    }
+    if (!tl.T) {
+      batch_free(b);
+      return fail(STAP_ERR_INVALID_ARG, "tile %d: T is NULL", t);
+    }
+    const stap_config& c = tl.plan->cfg;
+    const int cls = kstap::kernel_class(c.p, c.q, c.r_b, c.precision);
+    if (cls < 0) {
+      batch_free(b);
+      return fail(STAP_ERR_UNSUPPORTED, "tile %d: no kernel for p=%d q=%d r_b=%d", t, c.p, c.q, c.r_b);
+    }
+    kstap::KParams k;
+    fill_params(tl.plan, tl.x, tl.H, tl.W, &k);
+    k.T = tl.T;
+    k.D = tl.D;
+    k.range_first = 0;
+    k.range_end = int64_t(tl.H) * tl.W;
+    b->descs.push_back(k);
+    b->pixels += int64_t(tl.H) * tl.W;
+    const double pq = double(c.p) * c.q;
+    cost[t] = double(tl.H) * tl.W * c.n * pq * pq;
+    auto it = cls_index.find(cls);
+    if (it == cls_index.end()) {
+      cls_index[cls] = int(b->classes.size());
+      b->classes.push_back(BatchClass());
+      b->classes.back().cls = cls;
+      it = cls_index.find(cls);
+    }
+    b->classes[it->second].order.push_back(t);
   }
+  char sig[64];
+  std::string signature;
+  for (BatchClass& c : b->classes) {
+    std::stable_sort(c.order.begin(), c.order.end(), [&](int32_t a, int32_t z) { return cost[a] > cost[z]; });
+    snprintf(sig, sizeof(sig), "c%d:%zu;", c.cls, c.order.size());
+    signature += sig;
+  }
+  snprintf(sig, sizeof(sig), "px%lld", (long long)(b->pixels >> 16));
+  b->signature = signature + sig;
+  b->ppb = 16;
+  b->grid_mult = 1;
+  if (pix_per_item > 0) {
+    b->ppb = pix_per_item;
+  } else {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(b->signature);
+    if (it != g_tune_cache.end()) {
+      b->ppb = it->second.first;
+      b->grid_mult = it->second.second;
+    }
+  }
+  // device buffer: descs | order | prefix | counters
+  size_t n_order = 0, n_prefix = 0;
+  for (const BatchClass& c : b->classes) {
+    b->order_base.push_back(n_order);
+    n_order += c.order.size();
+    n_prefix += c.order.size() + 1;
+  }
+  const size_t o_order = sizeof(kstap::KParams) * b->descs.size();
+  const size_t o_prefix = (o_order + sizeof(int32_t) * n_order + 15) / 16 * 16;
+  const size_t o_ctr = (o_prefix + sizeof(int64_t) * n_prefix + 15) / 16 * 16;
+  const size_t bytes = o_ctr + sizeof(unsigned long long) * b->classes.size();
+  hipError_t e = hipMalloc(&b->d_buf, bytes);
+  if (e != hipSuccess) {
+    b->d_buf = nullptr;
+    batch_free(b);
+    return fail(STAP_ERR_OUT_OF_MEMORY, "device tile table (%zu bytes): %s", bytes, hipGetErrorString(e));
+  }
+  char* base = static_cast<char*>(b->d_buf);
+  b->d_descs = reinterpret_cast<kstap::KParams*>(base);
+  b->d_order = reinterpret_cast<int32_t*>(base + o_order);
+  b->d_prefix = reinterpret_cast<int64_t*>(base + o_prefix);
+  b->d_counters = reinterpret_cast<unsigned long long*>(base + o_ctr);
+  std::vector<int32_t> order;
+  for (const BatchClass& c : b->classes) order.insert(order.end(), c.order.begin(), c.order.end());
+  e = hipMemcpy(b->d_descs, b->descs.data(), o_order, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * n_order, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    batch_free(b);
+    return fail(STAP_ERR_DEVICE, "batch set-up: %s", hipGetErrorString(e));
+  }
+  stap_status st = batch_build(b);
+  if (st != STAP_OK) {
+    std::string msg = last_error();
+    batch_free(b);
+    return fail(st, "%s", msg.c_str());
+  }
+  *out = b;
   return ok();
+}
+
+stap_status stap_batch_launch(stap_batch_t* batch, void* hip_stream) {
+  if (!batch || !batch->exec) return fail(STAP_ERR_INVALID_ARG, "batch is NULL or not built");
+  hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "graph launch: %s", hipGetErrorString(e));
+  return ok();
+}
+
+stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best_ppb, int32_t* best_grid_mult,
+                            double* best_ms) {
+  if (!batch) return fail(STAP_ERR_INVALID_ARG, "batch is NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(STAP_ERR_DEVICE, "event create failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(STAP_ERR_DEVICE, "event create failed");
+  }
+  const int ppbs[] = {4, 8, 16, 32};
+  const int mults[] = {1, 2};
+  double best = 1e300;
+  int bp = batch->ppb, bm = batch->grid_mult;
+  stap_status st = STAP_OK;
+  for (int ppb : ppbs) {
+    for (int m : mults) {
+      batch->ppb = ppb;
+      batch->grid_mult = m;
+      st = batch_tables(batch);
+      if (st == STAP_OK) st = batch_launch_direct(batch, s);   // warm-up
+      hipError_t e = hipSuccess;
+      float ms = 0.f;
+      if (st == STAP_OK) e = hipEventRecord(e0, s);
+      for (int r = 0; r < 2 && st == STAP_OK && e == hipSuccess; ++r) st = batch_launch_direct(batch, s);
+      if (st == STAP_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+      if (st == STAP_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+      if (st == STAP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (st != STAP_OK) break;
+      if (e != hipSuccess) {
+        st = fail(STAP_ERR_DEVICE, "tuning launch: %s", hipGetErrorString(e));
+        break;
+      }
+      if (ms / 2.0 < best) {
+        best = ms / 2.0;
+        bp = ppb;
+        bm = m;
+      }
+    }
+    if (st != STAP_OK) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != STAP_OK) return st;
+  batch->ppb = bp;
+  batch->grid_mult = bm;
+  hipError_t se = hipStreamSynchronize(s);
+  if (se != hipSuccess) return fail(STAP_ERR_DEVICE, "tuning: %s", hipGetErrorString(se));
+  st = batch_build(batch);
+  if (st != STAP_OK) return st;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[batch->signature] = {bp, bm};
+  }
+  if (best_ppb) *best_ppb = bp;
+  if (best_grid_mult) *best_grid_mult = bm;
+  if (best_ms) *best_ms = best;
+  return ok();
+}
+
+stap_status stap_batch_info(const stap_batch_t* batch, int64_t* pixels, int32_t* classes, int32_t* pix_per_item,
+                            int32_t* grid_mult) {
+  if (!batch) return fail(STAP_ERR_INVALID_ARG, "batch is NULL");
+  if (pixels) *pixels = batch->pixels;
+  if (classes) *classes = int32_t(batch->classes.size());
+  if (pix_per_item) *pix_per_item = batch->ppb;
+  if (grid_mult) *grid_mult = batch->grid_mult;
+  return ok();
+}
+
+stap_status stap_batch_destroy(stap_batch_t* batch) {
+  batch_free(batch);
+  return ok();
+}
+
+stap_status stap_run_batch(const stap_tile* tiles, int32_t ntiles, void* hip_stream) {
+  stap_batch_t* b = nullptr;
+  stap_status st = stap_batch_create(tiles, ntiles, 0, &b);
+  if (st != STAP_OK) return st;
+  st = stap_batch_launch(b, hip_stream);
+  if (st == STAP_OK) {
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) st = fail(STAP_ERR_DEVICE, "batch execution: %s", hipGetErrorString(e));
+  }
+  batch_free(b);
+  return st == STAP_OK ? ok() : st;
 }
 
 const char* stap_version(void) { return "kstap 0.1 (gfx950)"; }
 
-const char* stap_last_error(void) { return g_last_error.c_str(); }
+const char* stap_last_error(void) { return last_error().c_str(); }
 
 }  // extern "C"

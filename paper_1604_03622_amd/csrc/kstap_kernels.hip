@@ -199,8 +199,9 @@ __device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
 // row k of the orthonormal basis v (CGS2 orthonormalisation).  `cold` starts from M * Omega (Omega a
 // fixed generic block); otherwise v is the warm start.  A group has converged
 // when ||M V - V (V^H M V)||_F <= tol ||M V||_F for the basis entering a step;
-// that step's orthonormalised M V is kept.  The loop runs until every group
-// has converged or max_steps.  sV: LDS scratch of RM * D * (64 / QP) float2.
+// that step's orthonormalised M V is kept and the group's basis is frozen.
+// The loop runs until every group has converged or max_steps; each group's
+// result is the one it would reach alone.  sV: LDS scratch of RM * D * (64 / QP) float2.
 template <int RM, int QP, int D, typename C>
 __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_ok, int r, C (&v)[RM],
                                               C* sV, bool cold, int max_steps, double tol) {
@@ -212,6 +213,7 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
     for (int c = 0; c < RM; ++c) v[c] = (row_ok && c < r) ? cto<C>(omega(k, c)) : czero<C>();
   }
   bool tested = !cold;
+  bool done = false;
   int step = 0;
   while (true) {
     if (row_ok) {
@@ -226,9 +228,14 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
     if (row_ok) {
 #pragma unroll
       for (int l = 0; l < D; ++l) {
+        float2 m = mrow[l];
+        // keep the widening of the matrix row inside the loop (an empty asm
+        // makes the value opaque), so it is not hoisted into extra registers
+        asm volatile("" : "+v"(m.x), "+v"(m.y));
+        const C mc = cto<C>(m);
 #pragma unroll
         for (int c = 0; c < RM; ++c)
-          if (c < r) w[c] = cfma(cto<C>(mrow[l]), sV[(c * D + l) * G + g], w[c]);
+          if (c < r) w[c] = cfma(mc, sV[(c * D + l) * G + g], w[c]);
       }
     }
     wave_sync();
@@ -257,12 +264,16 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
       conv = rn <= S(tol * tol) * wn;
     }
     orth_cgs2<RM, QP, C>(w, r, row_ok);
+    // a group keeps the first basis computed from a converged one and is
+    // frozen from then on, so its result does not depend on its neighbours
+    if (!done) {
 #pragma unroll
-    for (int c = 0; c < RM; ++c) v[c] = w[c];
+      for (int c = 0; c < RM; ++c) v[c] = w[c];
+    }
+    done = done || conv;
     tested = true;
     ++step;
-    const bool all = __ballot(!conv) == 0;
-    if (all || step >= max_steps) break;
+    if (__ballot(!done) == 0 || step >= max_steps) break;
   }
   return step;
 }
@@ -584,41 +595,65 @@ template <typename T, typename F> struct Pick<false, T, F> { using type = F; };
 
 // PREC 0: FP32 covariance, FP32 eigensolves and statistic.
 // PREC 1: split-BF16 covariance, FP64 eigensolves and statistic.
+// LDS carve-out of one pixel pipeline (one workgroup), largest alignment first.
+template <int P, int Q, int RBM, int PREC>
+struct Lds {
+  using EC = typename Pick<PREC == 1, double2, float2>::type;
+  static constexpr int PQ = P * Q;
+  static constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
+  static constexpr int G = Groups<Q>::G;
+  static constexpr bool kTailInS = sizeof(EC) * RBM * Q * G <= sizeof(float2) * PQ * PQ;
+  static constexpr size_t oUA = 0;                                        // EC[P*RAM]
+  static constexpr size_t oAh = oUA + sizeof(EC) * P * RAM;               // EC[P*P]
+  static constexpr size_t oVa = oAh + sizeof(EC) * P * P;                 // EC[P*RAM]
+  static constexpr size_t oQUA = oVa + sizeof(EC) * P * RAM;              // EC[G][P*RAM]
+  static constexpr size_t oVt = oQUA + sizeof(EC) * G * P * RAM;          // EC[RBM*Q*G] unless in S
+  static constexpr size_t oS = oVt + (kTailInS ? 0 : sizeof(EC) * RBM * Q * G);   // float2[PQ*PQ]
+  static constexpr size_t oA = oS + sizeof(float2) * PQ * PQ;             // float2[P*P]
+  static constexpr size_t oQidx = oA + sizeof(float2) * P * P;            // int64[G]
+  static constexpr size_t oOff = oQidx + sizeof(int64_t) * G;             // int[kMaxN]
+  static constexpr size_t oQflag = oOff + sizeof(int) * kMaxN;            // int[G]
+  static constexpr size_t oQit = oQflag + sizeof(int) * G;                // int[G]
+  static constexpr size_t oQeta = oQit + sizeof(int) * G;                 // float[G]
+  static constexpr size_t bytes = ((oQeta + sizeof(float) * G) + 15) / 16 * 16;
+};
+
+// The whole per-pixel pass for `count` pixels starting at `first`: row-major
+// pixel indices of the frame (run mode) or positions in the pixel list (probe
+// mode).  One 64-lane workgroup; `lds` holds Lds<...>::bytes.
 template <int P, int Q, int RBM, int MODE, int PREC>
-__global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
+__device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, int64_t count, char* lds) {
   using EC = typename Pick<PREC == 1, double2, float2>::type;   // eigensolver / statistic precision
   using ES = decltype(EC{}.x);
+  using L = Lds<P, Q, RBM, PREC>;
   constexpr int PQ = P * Q;
   constexpr int NB = (PQ + 15) / 16;        // 16-row blocks of the pq x pq covariance
-  constexpr int NT = NB * (NB + 1) / 2;     // upper tiles of Re S
-  constexpr int NO = NB * (NB - 1) / 2;     // strictly upper tiles of Im S
   constexpr int QQ = Q * Q;
   constexpr int NE = (QQ + 63) / 64;        // q x q entries per lane
-  constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
+  constexpr int RAM = L::RAM;
   constexpr int QP = Groups<Q>::QP;         // lanes per pixel in the batched tail
   constexpr int G = Groups<Q>::G;           // pixels per batched tail
   static_assert(PQ * PQ >= QQ, "LDS reuse");
-  constexpr bool kTailInS = sizeof(EC) * RBM * Q * G <= sizeof(float2) * PQ * PQ;
 
-  __shared__ float2 sS[PQ * PQ];            // S; then raw B; then tail scratch
-  __shared__ int sOff[kMaxN];
-  __shared__ float2 sA[P * P];
-  __shared__ EC sUA[P * RAM];
-  __shared__ EC sAh[P * P];
-  __shared__ EC sVa[P * RAM];
-  __shared__ EC sQUA[G][P * RAM];           // queued pixels: U_A
-  __shared__ EC sVt[kTailInS ? 1 : RBM * Q * G];
-  EC* const tail_scratch = kTailInS ? reinterpret_cast<EC*>(sS) : sVt;
-  __shared__ int64_t sQidx[G];              //                pixel index
-  __shared__ int sQflag[G];                 //                0 ok, 1 zero training, 2 non-finite
-  __shared__ float sQeta[G];
-  __shared__ int sQit[G];
+  float2* const sS = reinterpret_cast<float2*>(lds + L::oS);     // S; then raw B; then tail scratch
+  int* const sOff = reinterpret_cast<int*>(lds + L::oOff);
+  float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
+  EC* const sUA = reinterpret_cast<EC*>(lds + L::oUA);
+  EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
+  EC* const sVa = reinterpret_cast<EC*>(lds + L::oVa);
+  EC (*const sQUA)[P * RAM] = reinterpret_cast<EC (*)[P * RAM]>(lds + L::oQUA);   // queued pixels: U_A
+  EC* const tail_scratch = L::kTailInS ? reinterpret_cast<EC*>(sS) : reinterpret_cast<EC*>(lds + L::oVt);
+  int64_t* const sQidx = reinterpret_cast<int64_t*>(lds + L::oQidx);             //   pixel index
+  int* const sQflag = reinterpret_cast<int*>(lds + L::oQflag);                   //   0 ok, 1 zero, 2 non-finite
+  float* const sQeta = reinterpret_cast<float*>(lds + L::oQeta);
+  int* const sQit = reinterpret_cast<int*>(lds + L::oQit);
 
   const int lane = threadIdx.x;
   const int n = prm.n;
   const int H = prm.H, W = prm.W;
   const int r_a = prm.r_a, r_b = prm.r_b;
 
+  wave_sync();
   for (int m = lane; m < n; m += 64) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
   wave_sync();
 
@@ -632,22 +667,6 @@ __global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
     row_ok[I] = rho < PQ;
     const int ch = rho / Q, j = rho - ch * Q;
     chan_off[I] = row_ok[I] ? ch * H * W * Q + j : 0;
-  }
-
-  // pixel schedule
-  int64_t first, count;
-  if (MODE == kModeRun) {
-    const int per = gridDim.x >> 3;   // grid is a multiple of 8 (one share per XCD)
-    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    if (logical >= prm.nlogical) return;
-    const int64_t total = int64_t(H) * W;
-    first = int64_t(logical) * prm.pix_per_block;
-    count = total - first;
-    if (count > prm.pix_per_block) count = prm.pix_per_block;
-  } else {
-    first = int64_t(blockIdx.x) * prm.pix_per_block;
-    count = prm.npix - first;
-    if (count > prm.pix_per_block) count = prm.pix_per_block;
   }
 
   // queue of pixels waiting for the batched tail: lane (g, k) holds row k of
@@ -1047,6 +1066,63 @@ __global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
   if (nq > 0) tail(nq);
 }
 
+// Whole frame (run mode) or pixel list (probe mode).  Run mode: workgroup ids
+// are remapped so each of the 8 XCDs takes a contiguous share of the frame.
+template <int P, int Q, int RBM, int MODE, int PREC>
+__global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
+  __shared__ __attribute__((aligned(16))) char lds[Lds<P, Q, RBM, PREC>::bytes];
+  int64_t first, count;
+  if (MODE == kModeRun) {
+    const int per = gridDim.x >> 3;   // grid is a multiple of 8 (one share per XCD)
+    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (logical >= prm.nlogical) return;
+    const int64_t total = int64_t(prm.H) * prm.W;
+    first = int64_t(logical) * prm.pix_per_block;
+    count = total - first;
+    if (count > prm.pix_per_block) count = prm.pix_per_block;
+  } else {
+    first = int64_t(blockIdx.x) * prm.pix_per_block;
+    count = prm.npix - first;
+    if (count > prm.pix_per_block) count = prm.pix_per_block;
+  }
+  run_pixels<P, Q, RBM, MODE, PREC>(prm, first, count, lds);
+}
+
+// Persistent batched kernel: every workgroup pops work items (runs of `ppb`
+// consecutive pixels of one tile's range [range_first, range_end)) from a
+// device counter until the queue is empty.  Items are numbered tile after tile in the order of `order` (longest
+// tiles first); prefix[j] is the first item of order[j] (prefix[nt] = total).
+template <int P, int Q, int RBM, int PREC>
+__global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restrict__ descs,
+                                                          const int32_t* __restrict__ order,
+                                                          const int64_t* __restrict__ prefix, int nt,
+                                                          int ppb, unsigned long long* counter) {
+  __shared__ __attribute__((aligned(16))) char lds[Lds<P, Q, RBM, PREC>::bytes];
+  __shared__ long long s_item;
+  const int64_t total = prefix[nt];
+  while (true) {
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+    wave_sync();
+    const int64_t item = s_item;
+    wave_sync();
+    if (item >= total) break;
+    int lo = 0, hi = nt - 1;   // last j with prefix[j] <= item
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (prefix[mid] <= item) lo = mid; else hi = mid - 1;
+    }
+    const KParams& prm = descs[order[lo]];
+    const int64_t first = prm.range_first + (item - prefix[lo]) * ppb;
+    int64_t count = prm.range_end - first;
+    if (count > ppb) count = ppb;
+    run_pixels<P, Q, RBM, kModeRun, PREC>(prm, first, count, lds);
+  }
+}
+
+__global__ void reset_counters(unsigned long long* c, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
+}
+
 // ---------------------------------------------------------------- dispatch
 template <int P, int Q, int RBM, int PREC>
 int launch_one(int mode, const KParams& prm, hipStream_t stream) {
@@ -1061,12 +1137,24 @@ int launch_one(int mode, const KParams& prm, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <int P, int Q, int RBM, int PREC>
+int launch_persist(const KParams* descs, const int32_t* order, const int64_t* prefix, int nt, int ppb,
+                   unsigned long long* counter, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL((kstap_persistent<P, Q, RBM, PREC>), dim3(grid), dim3(64), 0, stream, descs, order, prefix, nt,
+                     ppb, counter);
+  return hipGetLastError();
+}
+
 struct Entry {
   int p, q, rbm, prec;
   int (*fn)(int, const KParams&, hipStream_t);
+  int (*persist)(const KParams*, const int32_t*, const int64_t*, int, int, unsigned long long*, int, hipStream_t);
+  const void* persist_fn;
 };
 
-#define KSTAP_ENTRY(P, Q, R, X) {P, Q, R, X, &launch_one<P, Q, R, X>}
+#define KSTAP_ENTRY(P, Q, R, X) \
+  {P, Q, R, X, &launch_one<P, Q, R, X>, &launch_persist<P, Q, R, X>, \
+   reinterpret_cast<const void*>(&kstap_persistent<P, Q, R, X>)}
 const Entry kTable[] = {
     KSTAP_ENTRY(2, 8, 4, 0),  KSTAP_ENTRY(2, 16, 4, 0), KSTAP_ENTRY(2, 32, 4, 0),
     KSTAP_ENTRY(3, 8, 4, 0),  KSTAP_ENTRY(3, 8, 8, 0),  KSTAP_ENTRY(3, 12, 4, 0), KSTAP_ENTRY(3, 12, 8, 0),
@@ -1092,6 +1180,29 @@ int launch_pixels(int p, int q, int precision, int mode, const KParams& prm, hip
   const Entry* e = find(p, q, prm.r_b, precision);
   if (!e) return hipErrorInvalidValue;
   return e->fn(mode, prm, stream);
+}
+
+int kernel_class(int p, int q, int r_b, int precision) {
+  const Entry* e = find(p, q, r_b, precision);
+  return e ? int(e - kTable) : -1;
+}
+
+int launch_persistent(int cls, const KParams* descs, const int32_t* order, const int64_t* prefix, int nt, int ppb,
+                      unsigned long long* counter, int grid, hipStream_t stream) {
+  if (cls < 0 || cls >= int(sizeof(kTable) / sizeof(kTable[0]))) return hipErrorInvalidValue;
+  return kTable[cls].persist(descs, order, prefix, nt, ppb, counter, grid, stream);
+}
+
+const void* persistent_kernel(int cls) {
+  if (cls < 0 || cls >= int(sizeof(kTable) / sizeof(kTable[0]))) return nullptr;
+  return kTable[cls].persist_fn;
+}
+
+const void* reset_kernel() { return reinterpret_cast<const void*>(&reset_counters); }
+
+int launch_reset(unsigned long long* counters, int n, hipStream_t stream) {
+  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counters, n);
+  return hipGetLastError();
 }
 
 }  // namespace kstap

@@ -69,3 +69,31 @@ def test_run_rejects_bad_arguments_without_touching_a_device():
     out = kstap.StapProbeOut(None, None, None, None, None)
     assert L.stap_probe(plan.handle, ctypes.c_void_p(16), 64, 64, ctypes.c_void_p(16), 3, ctypes.byref(out), None) == 1
     assert L.stap_probe(plan.handle, ctypes.c_void_p(16), 64, 64, None, -1, None, None) == 1
+
+
+def test_batch_rejects_bad_arguments_without_a_device():
+    L = kstap.lib()
+    h = ctypes.c_void_p()
+    assert L.stap_batch_create(None, 0, 0, ctypes.byref(h)) == 1
+    arr = (kstap.StapTile * 1)()
+    arr[0] = kstap.StapTile(None, 16, 8, 8, 16, None)
+    assert L.stap_batch_create(arr, 1, 0, ctypes.byref(h)) == 1
+    assert L.stap_batch_create(arr, 1, -3, ctypes.byref(h)) == 1
+    assert L.stap_batch_launch(None, None) == 1
+    assert L.stap_batch_tune(None, None, None, None, None) == 1
+    assert L.stap_batch_destroy(None) == 0
+    assert L.stap_run_batch(None, 0, None) == 1
+
+
+def test_server_rejects_bad_arguments_without_a_device():
+    L = kstap.lib()
+    h = ctypes.c_void_p()
+    assert L.stap_server_create(1 << 10, 4, 0, ctypes.byref(h)) == 1
+    assert L.stap_server_create(1 << 30, 0, 0, ctypes.byref(h)) == 1
+    assert L.stap_server_create(1 << 30, 4, -1, ctypes.byref(h)) == 1
+    assert L.stap_server_create(1 << 30, 4, 0, None) == 1
+    t = ctypes.c_uint64()
+    assert L.stap_server_submit(None, None, None, 8, 8, 0, None, None, ctypes.byref(t)) == 1
+    assert L.stap_server_wait(None, 1, 0, None) == 1
+    assert L.stap_server_stats(None, None, None, None, None) == 1
+    assert L.stap_server_destroy(None) == 0

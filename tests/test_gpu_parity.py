@@ -261,3 +261,50 @@ def test_repeatable_bitwise():
     T2, _ = kstap.run(plan, xd)
     torch.cuda.synchronize()
     assert torch.equal(T1, T2)
+
+
+# -------------------------------------------------------- mixed precision
+@pytest.mark.parametrize("case", ["tiny", "frame_q16", "q12_rb6", "q8_rb8_ra2", "fixed_h"])
+def test_mixed_precision_parity(case):
+    """Split-BF16 covariance (three products, FP32 accumulation) with FP64
+    eigensolves and statistic, against the FP64 oracle at the same 1e-4 bar;
+    per-output errors (T, U_A and U_B projectors, eta, iterations) reported."""
+    kstap = _kstap()
+    if case == "tiny":
+        spec = scenegen.TINY
+        base = dict(p=3, q=8, n=64, r_a=1, r_b=3)
+    elif case == "frame_q16":
+        spec = scenegen.SceneSpec(p=3, q=16, H=72, W=72, r_a=1, r_b=4, n_targets=6, snr_db=(0.0, 15.0), block=24)
+        base = dict(p=3, q=16, n=200, r_a=1, r_b=4)
+    elif case == "q12_rb6":
+        spec = scenegen.SceneSpec(p=3, q=12, H=44, W=40, r_a=1, r_b=6, n_targets=4)
+        base = dict(p=3, q=12, n=128, r_a=1, r_b=6)
+    elif case == "q8_rb8_ra2":
+        spec = scenegen.SceneSpec(p=3, q=8, H=40, W=40, r_a=2, r_b=5, n_targets=4)
+        base = dict(p=3, q=8, n=64, r_a=2, r_b=5)
+    else:
+        spec = scenegen.SceneSpec(p=3, q=16, H=40, W=40, r_a=1, r_b=4, n_targets=4)
+        base = dict(p=3, q=16, n=200, r_a=1, r_b=4, stat_mode="fixed", h_steer=np.exp(0.6j * np.arange(3)))
+    sc = scenegen.make_scene(spec, seed=scenegen.BASE_SEED + 50 + len(case))
+    plan = kstap.Plan(**base, precision="bf16x3")
+    ocfg = oracle.OracleConfig(**base)
+    note(f"mixed {case}")
+    Tg, Dg, xd = run_frame(plan, sc.x)
+    ref, out = frame_oracle(sc.x, ocfg)
+    check_parity(Tg.ravel(), Dg.ravel(), ref, plan.tau, base["r_a"], base["r_b"], "bf16x3 " + case)
+    # per-output report on the valid pixels through the probe
+    pix = out["pixels"]
+    pr = kstap.probe(plan, xd, pix)
+    torch.cuda.synchronize()
+    g = graded_mask(dict(T=out["T"], lam_A=out["lam_A"], lam_B=out["lam_B"], valid=np.ones(len(pix), bool)),
+                    base["r_a"], base["r_b"])
+    UA = pr["U_A"].cpu().numpy().astype(np.complex128)
+    UB = pr["U_B"].cpu().numpy().astype(np.complex128)
+    dA = np.abs(UA @ np.conj(np.swapaxes(UA, 1, 2)) - out["U_A"] @ np.conj(np.swapaxes(out["U_A"], 1, 2))).max(axis=(1, 2))
+    dB = np.abs(UB @ np.conj(np.swapaxes(UB, 1, 2)) - out["U_B"] @ np.conj(np.swapaxes(out["U_B"], 1, 2))).max(axis=(1, 2))
+    eT = rel_err(pr["T"].cpu().numpy().astype(np.float64), out["T"])
+    eeta = np.abs(pr["eta"].cpu().numpy() - out["eta"]) / np.maximum(out["eta"], 1e-12)
+    it = np.abs(pr["iters"].cpu().numpy() - out["iters"])
+    note(f"[bf16x3 {case}] per-output max error over {int(g.sum())} graded px: T {eT[g].max():.2e}, "
+         f"P_A {dA[g].max():.2e}, P_B {dB[g].max():.2e}, eta(rel) {eeta[g].max():.2e}, iters diff {it[g].max()}")
+    assert eT[g].max() <= TOL and dA[g].max() <= 1e-4 and dB[g].max() <= 1e-4
