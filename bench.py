@@ -79,6 +79,180 @@ def cpu_baseline(x, plan_kw, count, seed=123):
                 sample=f"{done} seeded valid pixels of the same frame, FP64 NumPy, {dt:.1f} s wall")
 
 
+# ------------------------------------------------------------ system forms
+def _timed(torch, fn, reps):
+    fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps / 1e3
+
+
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def form_frame_mixed(kstap, torch, scene, steps):
+    """The same full frame with split-BF16 covariance and FP64 eigensolves."""
+    x = torch.from_numpy(scene.x).cuda()
+    plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4, precision="bf16x3")
+    T = torch.empty(x.shape[1:3], device="cuda")
+    D = torch.empty(x.shape[1:3], dtype=torch.uint8, device="cuda")
+    r0, r1, c0, c1 = plan.valid_region(x.shape[1], x.shape[2])
+    sec = _timed(torch, lambda: kstap.run(plan, x, T, D), steps)
+    px = (r1 - r0) * (c1 - c0)
+    flops = scm_flops_per_pixel(3, 16, 200) * px
+    return dict(workload="full frame 2048x2048 p=3 q=16 n=200, bf16x3 covariance + FP64 eigensolves",
+                pixels_per_s=px / sec, ms=sec * 1e3,
+                scm_tflops_credited=flops / sec / 1e12,
+                frac_bf16x3_roof=(flops / sec / 1e12) / (2500.0 / 3.0),
+                frac_bf16_k1_roof=(flops / sec / 1e12) / 2500.0)
+
+
+def form_wide_mixed(kstap, torch, steps):
+    """Mixed-precision workload: p=5, q=24 (pq=120), 1024 x 1024, n=256, split-BF16
+    covariance with FP64 eigensolves, against the plain FP32 path on the same frame."""
+    sc = scenegen.make_scene(scenegen.MIXED)
+    x = torch.from_numpy(sc.x).cuda()
+    del sc
+    out = dict(workload="p=5 q=24 1024x1024 complex64, n=256, r_a=1 r_b=4")
+    for prec in ("fp32", "bf16x3"):
+        plan = kstap.Plan(p=5, q=24, n=256, r_a=1, r_b=4, precision=prec)
+        T = torch.empty(x.shape[1:3], device="cuda")
+        D = torch.empty(x.shape[1:3], dtype=torch.uint8, device="cuda")
+        r0, r1, c0, c1 = plan.valid_region(x.shape[1], x.shape[2])
+        px = (r1 - r0) * (c1 - c0)
+        sec = _timed(torch, lambda: kstap.run(plan, x, T, D), steps)
+        tfl = scm_flops_per_pixel(5, 24, 256) * px / sec / 1e12
+        out[prec] = dict(pixels_per_s=px / sec, ms=sec * 1e3, scm_tflops_credited=tfl)
+        _log(f"wide {prec}: {px / sec / 1e6:.2f} Mpx/s")
+    out["bf16x3"]["frac_bf16x3_roof"] = out["bf16x3"]["scm_tflops_credited"] / (2500.0 / 3.0)
+    out["fp32"]["frac_fp32_mfma_roof"] = out["fp32"]["scm_tflops_credited"] / MFMA_FP32_PEAK_TFLOPS
+    return out
+
+
+def form_batch(kstap, torch):
+    """64 uneven tiles: per-tile plain FP32 path vs one batched launch (FP32
+    and split-BF16)."""
+    specs = scenegen.batch_tile_specs()
+    xs, outs = [], []
+    for i, (sp, n) in enumerate(specs):
+        xs.append(scenegen.make_scene_torch(sp, seed=scenegen.BASE_SEED + 100 + i))
+        outs.append((torch.empty((sp.H, sp.W), device="cuda"), torch.empty((sp.H, sp.W), dtype=torch.uint8, device="cuda")))
+    torch.cuda.synchronize()
+    px = sum(sp.H * sp.W for sp, _ in specs)
+    res = dict(workload=f"{len(specs)} tiles, side in {{128..1024}}, q in {{8,12,16}}, n in {{64,128,256}}, "
+                        f"r_a in {{1,2}}, r_b in {{2..6}}", pixels=px)
+    for prec in ("fp32", "bf16x3"):
+        plans = [kstap.Plan(p=3, q=sp.q, n=n, r_a=sp.r_a, r_b=sp.r_b, precision=prec) for sp, n in specs]
+        tiles = [(pl, x, T, D) for pl, x, (T, D) in zip(plans, xs, outs)]
+        if prec == "fp32":
+            sec = _timed(torch, lambda: [kstap.run(pl, x, T, D) for pl, x, T, D in tiles], 2)
+            res["per_tile_fp32_pixels_per_s"] = px / sec
+        b = kstap.Batch(tiles)
+        tuned = b.tune()
+        sec = _timed(torch, b.launch, 3)
+        res[f"batched_{prec}_pixels_per_s"] = px / sec
+        res[f"batched_{prec}_tuned"] = tuned
+        _log(f"batch {prec}: {px / sec / 1e6:.1f} Mpx/s")
+    return res
+
+
+def form_serving(kstap, torch, nframes):
+    """Poisson stream (and a burst) of frames of mixed sizes through the
+    continuous-batching server vs the plain per-frame path (upload, run,
+    download, one frame at a time), same arrival trace, latency = submit to
+    results in host memory."""
+    import threading
+    trace = scenegen.serving_trace()[:nframes]
+    frames = []
+    for i, (sp, n) in enumerate(trace):
+        xd = scenegen.make_scene_torch(sp, seed=scenegen.BASE_SEED + 500 + i)
+        xh = torch.empty(xd.shape, dtype=torch.complex64, pin_memory=True)
+        xh.copy_(xd)
+        del xd
+        frames.append((kstap.Plan(p=3, q=sp.q, n=n, r_a=1, r_b=3), xh, sp.H * sp.W))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    tot_px = sum(f[2] for f in frames)
+    mean_px = tot_px / len(frames)
+
+    def plain(arrivals):
+        lat = []
+        t0 = time.perf_counter()
+        for (pl, xh, npx), ta in zip(frames, arrivals):
+            now = time.perf_counter() - t0
+            if ta > now:
+                time.sleep(ta - now)
+            xd = xh.to("cuda", non_blocking=True)
+            T, D = kstap.run(pl, xd)
+            Th, Dh = T.cpu(), D.cpu()
+            lat.append(time.perf_counter() - t0 - ta)
+            del xd
+        span = time.perf_counter() - t0
+        return lat, span
+
+    def served(arrivals):
+        srv = kstap.Server(hbm_budget_bytes=24 << 30, max_inflight=16, step_pixels=1 << 20)
+        tickets = []
+        t0 = time.perf_counter()
+
+        def submit():
+            for (pl, xh, npx), ta in zip(frames, arrivals):
+                now = time.perf_counter() - t0
+                if ta > now:
+                    time.sleep(ta - now)
+                tickets.append(srv.submit(pl, xh))
+        th = threading.Thread(target=submit)
+        th.start()
+        th.join()
+        lat = [srv.wait(t)[2] for t in tickets]
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        return lat, span, st
+
+    # capacity of the plain path on this trace (all frames queued at once)
+    lat0, span0 = plain([0.0] * len(frames))
+    cap_fps = len(frames) / span0
+    rate = 0.7 * cap_fps
+    rng = np.random.Generator(np.random.PCG64(scenegen.BASE_SEED + 9))
+    arr = np.cumsum(rng.exponential(1.0 / rate, len(frames)))
+    arr -= arr[0]
+    out = dict(workload=f"{len(frames)} frames, side U{{256..2048}}, q in {{8,16}}, n U{{64..256}}, p=3; "
+                        f"pinned host frames, latency = submit to results in host memory",
+               frames=len(frames), mean_pixels_per_frame=mean_px,
+               poisson_rate_fps=rate, rate_rule="0.7 x plain-path capacity on this trace")
+    for name, arrivals in (("burst", [0.0] * len(frames)), ("poisson", list(arr))):
+        pl_lat, pl_span = plain(arrivals)
+        sv_lat, sv_span, st = served(arrivals)
+        out[name] = dict(
+            plain=dict(pixels_per_s=tot_px / pl_span, p50_s=float(np.percentile(pl_lat, 50)),
+                       p99_s=float(np.percentile(pl_lat, 99))),
+            server=dict(pixels_per_s=tot_px / sv_span, p50_s=float(np.percentile(sv_lat, 50)),
+                        p99_s=float(np.percentile(sv_lat, 99)), server_stats=st))
+        _log(f"serving {name}: server {tot_px / sv_span / 1e6:.1f} Mpx/s p99 {np.percentile(sv_lat, 99) * 1e3:.0f} ms; "
+             f"plain {tot_px / pl_span / 1e6:.1f} Mpx/s p99 {np.percentile(pl_lat, 99) * 1e3:.0f} ms")
+    return out
+
+
+def system_forms(kstap, torch, args, scene):
+    forms = {}
+    forms["frame_bf16x3"] = form_frame_mixed(kstap, torch, scene, max(3, args.steps // 2))
+    _log(f"frame bf16x3: {forms['frame_bf16x3']['pixels_per_s'] / 1e6:.1f} Mpx/s")
+    torch.cuda.empty_cache()
+    forms["mixed_workload"] = form_wide_mixed(kstap, torch, 3)
+    torch.cuda.empty_cache()
+    forms["batch"] = form_batch(kstap, torch)
+    torch.cuda.empty_cache()
+    forms["serving"] = form_serving(kstap, torch, args.serve_frames)
+    return forms
+
+
 # ------------------------------------------------------------------- main
 def main():
     ap = argparse.ArgumentParser()
@@ -88,6 +262,10 @@ def main():
     ap.add_argument("--workload", default="full_frame", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=400000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched / served / mixed-precision legs")
+    ap.add_argument("--serve-frames", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -119,6 +297,11 @@ def main():
     T = torch.empty((H, W), dtype=torch.float32, device=dev)
     D = torch.empty((H, W), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         kstap.run(plan, x, T, D, stream=stream)
     torch.cuda.synchronize()
@@ -169,6 +352,10 @@ def main():
         },
         "cpu_baseline": cpu,
     }
+    if not args.no_forms:
+        del x
+        torch.cuda.empty_cache()
+        result["forms"] = system_forms(kstap, torch, args, scene)
     print(json.dumps(result), flush=True)
 
 

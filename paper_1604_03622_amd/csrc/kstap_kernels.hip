@@ -207,7 +207,7 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
                                               C* sV, bool cold, int max_steps, double tol) {
   using S = decltype(C{}.x);
   constexpr int G = 64 / QP;
-  const int lane = threadIdx.x, g = lane / QP, k = lane % QP;
+  const int lane = threadIdx.x & 63, g = lane / QP, k = lane % QP;   // lane within its wavefront
   if (cold) {
 #pragma unroll
     for (int c = 0; c < RM; ++c) v[c] = (row_ok && c < r) ? cto<C>(omega(k, c)) : czero<C>();
@@ -1119,6 +1119,639 @@ __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restr
   }
 }
 
+// ====================================================================
+// Wide pixels (p*q > 64): one 256-lane workgroup (4 wavefronts) per pixel.
+//
+// The covariance tiles (16 x 16, upper block-triangle) are dealt round-robin
+// to the 4 waves.  Training vectors are staged in LDS 16 at a time (split
+// BF16 hi/lo pairs for PREC 1, FP32 for PREC 0), double-buffered: the global
+// loads of the next chunk are in flight while the waves run the MFMAs of the
+// current one.  S is kept as its upper q x q blocks S(i,j), i <= j (the lower
+// blocks are their conjugate transposes), which halves its LDS footprint.
+// LR-Kron sweeps run over all 256 lanes with the block sums reduced across
+// waves through LDS; the small eigensolves and the statistic are computed
+// identically by every wave.
+// ====================================================================
+template <int P, int Q, int RBM, int PREC>
+struct WideLds {
+  using EC = typename Pick<PREC == 1, double2, float2>::type;
+  static constexpr int PQ = P * Q;
+  static constexpr int NB = (PQ + 15) / 16;
+  static constexpr int QS = Q + 1;                                   // padded block row
+  static constexpr int NBLK = P * (P + 1) / 2;
+  static constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
+  static constexpr size_t sS = sizeof(float2) * NBLK * Q * QS;       // upper blocks of S
+  // staging (aliases S): per buffer NB*16 rows x 16 vectors
+  static constexpr size_t rowb = PREC ? 80 : 144;                    // padded bytes per staged row
+  static constexpr size_t stage1 = PREC ? 2 * NB * 16 * rowb : NB * 16 * rowb;   // hi + lo, or fp32
+  static constexpr size_t sStage = 2 * stage1;
+  static constexpr size_t oS = 0;
+  static constexpr size_t oRed = ((sS > sStage ? sS : sStage) + 15) / 16 * 16;   // float[4][2*P*P + 8]
+  static constexpr int KRED = 2 * P * P + 8;
+  static constexpr size_t oRedD = oRed + sizeof(float) * 4 * KRED;  // double[4]
+  static constexpr size_t oUA = (oRedD + sizeof(double) * 4 + 15) / 16 * 16;      // EC[P*RAM]
+  static constexpr size_t oAh = oUA + sizeof(EC) * P * RAM;          // EC[P*P]
+  static constexpr size_t oVa = oAh + sizeof(EC) * P * P;            // EC[P*RAM]
+  static constexpr size_t oA = oVa + sizeof(EC) * P * RAM;           // float2[P*P]
+  static constexpr size_t oOff = oA + sizeof(float2) * P * P;        // int[kMaxN]
+  static constexpr size_t bytes = (oOff + sizeof(int) * kMaxN + 15) / 16 * 16;
+};
+
+__device__ __forceinline__ void block_sync() { __syncthreads(); }
+
+// Sums K values over the 256 lanes of the workgroup (every lane gets the sum).
+template <int K>
+__device__ __forceinline__ void block_sum(float (&v)[K], float* red) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wsum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
+  }
+  block_sync();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = (red[k] + red[K + k]) + (red[2 * K + k] + red[3 * K + k]);
+  block_sync();
+}
+__device__ __forceinline__ double block_sumd(double v, double* red) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  v = wsumd(v);
+  if (lane == 0) red[w] = v;
+  block_sync();
+  v = (red[0] + red[1]) + (red[2] + red[3]);
+  block_sync();
+  return v;
+}
+
+template <int P, int Q, int RBM, int MODE, int PREC>
+__device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t first, int64_t count, char* lds) {
+  using EC = typename Pick<PREC == 1, double2, float2>::type;
+  using ES = decltype(EC{}.x);
+  using L = WideLds<P, Q, RBM, PREC>;
+  constexpr int PQ = P * Q;
+  constexpr int NB = L::NB;
+  constexpr int QS = L::QS;
+  constexpr int QQ = Q * Q;
+  constexpr int NE = (QQ + 255) / 256;      // q x q entries per lane
+  constexpr int RAM = L::RAM;
+  constexpr int NPAIR = NB * (NB + 1) / 2;
+  constexpr int MYP = (NPAIR + 3) / 4;      // tile pairs per wave (round-robin)
+  constexpr int KRED = L::KRED;
+  constexpr int QP = Groups<Q>::QP;
+
+  float2* const sS = reinterpret_cast<float2*>(lds + L::oS);
+  char* const stage = lds + L::oS;
+  float* const red = reinterpret_cast<float*>(lds + L::oRed);
+  double* const redd = reinterpret_cast<double*>(lds + L::oRedD);
+  EC* const sUA = reinterpret_cast<EC*>(lds + L::oUA);
+  EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
+  EC* const sVa = reinterpret_cast<EC*>(lds + L::oVa);
+  float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
+  int* const sOff = reinterpret_cast<int*>(lds + L::oOff);
+
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int n = prm.n, H = prm.H, W = prm.W;
+  const int r_a = prm.r_a, r_b = prm.r_b;
+
+  block_sync();
+  for (int m = tid; m < n; m += 256) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
+  block_sync();
+
+  // this wave's tile pairs (I, J), I <= J, round-robin over the upper tiles
+  int pI[MYP], pJ[MYP];
+  bool pOk[MYP];
+  {
+    int t = 0;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = I; J < NB; ++J, ++t) {
+        if ((t & 3) == wave) {
+          pI[t >> 2] = I;
+          pJ[t >> 2] = J;
+        }
+      }
+#pragma unroll
+    for (int u = 0; u < MYP; ++u) pOk[u] = (u * 4 + wave) < NPAIR;
+  }
+
+  // staging items of this thread: (vector v, row rho) = divmod(tid + 256 it, PQ)
+  constexpr int NIT = (16 * PQ + 255) / 256;
+  int it_v[NIT], it_rho[NIT], it_off[NIT];
+  bool it_ok[NIT];
+#pragma unroll
+  for (int it = 0; it < NIT; ++it) {
+    const int idx = tid + 256 * it;
+    it_ok[it] = idx < 16 * PQ;
+    const int v = it_ok[it] ? idx / PQ : 0, rho = it_ok[it] ? idx - (idx / PQ) * PQ : 0;
+    it_v[it] = v;
+    it_rho[it] = rho;
+    const int ch = rho / Q, j = rho - (rho / Q) * Q;
+    it_off[it] = ch * H * W * Q + j;
+  }
+
+  for (int64_t itp = 0; itp < count; ++itp) {
+    const int64_t idx = first + itp;
+    int r, c;
+    if (MODE == kModeRun) {
+      r = int(idx / W);
+      c = int(idx - int64_t(r) * W);
+    } else {
+      r = prm.pix[2 * idx];
+      c = prm.pix[2 * idx + 1];
+    }
+    const bool valid = r >= prm.r0 && r < prm.r1 && c >= prm.c0 && c < prm.c1;
+    if (!valid) {
+      if (tid == 0) {
+        prm.T[idx] = 0.f;
+        if (MODE == kModeRun && prm.D) prm.D[idx] = 0;
+        if (MODE == kModeProbe) {
+          if (prm.eta) prm.eta[idx] = 0.f;
+          if (prm.iters) prm.iters[idx] = 0;
+        }
+      }
+      if (MODE == kModeProbe) {
+        if (prm.UA)
+          for (int e = tid; e < P * r_a; e += 256) prm.UA[idx * P * r_a + e] = cz();
+        if (prm.UB)
+          for (int e = tid; e < Q * r_b; e += 256) prm.UB[idx * Q * r_b + e] = cz();
+      }
+      continue;
+    }
+    const float2* xp = prm.x + (int64_t(r) * W + c) * Q;
+
+    // ------------------------------------------------------------ a2 SCM
+    f4 accR[MYP], accI[MYP];
+#pragma unroll
+    for (int u = 0; u < MYP; ++u) accR[u] = accI[u] = f4{0.f, 0.f, 0.f, 0.f};
+    const int nch = (n + 15) >> 4;
+    float2 pre[NIT];
+    auto gload = [&](int ch) {
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int m = ch * 16 + it_v[it];
+        const bool ok = it_ok[it] && m < n;
+        pre[it] = ok ? xp[it_off[it] + sOff[ok ? m : 0]] : cz();
+      }
+    };
+    auto sstore = [&](int buf) {
+      char* base = stage + buf * L::stage1;
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        if (!it_ok[it]) continue;
+        if constexpr (PREC == 1) {
+          const float a = pre[it].x, b = pre[it].y;
+          const __bf16 ha = (__bf16)a, hb = (__bf16)b;
+          const __bf16 la = (__bf16)(a - (float)ha), lb = (__bf16)(b - (float)hb);
+          __bf16* hrow = reinterpret_cast<__bf16*>(base + size_t(it_rho[it]) * L::rowb);
+          __bf16* lrow = reinterpret_cast<__bf16*>(base + size_t(NB * 16 + it_rho[it]) * L::rowb);
+          hrow[2 * it_v[it]] = ha;
+          hrow[2 * it_v[it] + 1] = hb;
+          lrow[2 * it_v[it]] = la;
+          lrow[2 * it_v[it] + 1] = lb;
+        } else {
+          float2* row = reinterpret_cast<float2*>(base + size_t(it_rho[it]) * L::rowb);
+          row[it_v[it]] = pre[it];
+        }
+      }
+    };
+    gload(0);
+    sstore(0);
+    block_sync();
+    for (int ch = 0; ch < nch; ++ch) {
+      const int buf = ch & 1;
+      if (ch + 1 < nch) gload(ch + 1);
+      const char* base = stage + buf * L::stage1;
+      const int g = lane >> 4, rr = lane & 15;
+      if constexpr (PREC == 1) {
+        // operand of block I: row 16 I + rr, vectors 4g..4g+3 (re, im) = 16 bytes
+        auto ld = [&](int I, bool lo) -> bf8 {
+          const int row = 16 * I + rr;
+          if (row >= PQ) return __builtin_bit_cast(bf8, u4{0u, 0u, 0u, 0u});
+          const char* p = base + size_t((lo ? NB * 16 : 0) + row) * L::rowb + g * 16;
+          return __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p));
+        };
+#pragma unroll
+        for (int u = 0; u < MYP; ++u) {
+          if (!pOk[u]) continue;
+          const bf8 hI = ld(pI[u], false), lI = ld(pI[u], true), hJ = ld(pJ[u], false), lJ = ld(pJ[u], true);
+          const bf8 zh = swap_neg(hI), zl = swap_neg(lI);
+          accR[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hI, hJ, accR[u], 0, 0, 0);
+          accI[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, hJ, accI[u], 0, 0, 0);
+          accR[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hI, lJ, accR[u], 0, 0, 0);
+          accI[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, lJ, accI[u], 0, 0, 0);
+          accR[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lI, hJ, accR[u], 0, 0, 0);
+          accI[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, hJ, accI[u], 0, 0, 0);
+        }
+      } else {
+        // 4 K-steps of 4 vectors: lane (row rr, vector 4 s + g)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          auto ld = [&](int I) -> float2 {
+            const int row = 16 * I + rr;
+            if (row >= PQ) return cz();
+            return reinterpret_cast<const float2*>(base + size_t(row) * L::rowb)[4 * s4 + g];
+          };
+#pragma unroll
+          for (int u = 0; u < MYP; ++u) {
+            if (!pOk[u]) continue;
+            const float2 a = ld(pI[u]), b = ld(pJ[u]);
+            accR[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accR[u], 0, 0, 0);
+            accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, accI[u], 0, 0, 0);
+            accR[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, accR[u], 0, 0, 0);
+            accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a.x, b.y, accI[u], 0, 0, 0);
+          }
+        }
+      }
+      if (ch + 1 < nch) sstore(buf ^ 1);
+      block_sync();
+    }
+    // S to LDS as upper blocks (the staging area is dead after the barrier above)
+    {
+      const float inv_n = 1.f / float(n);
+      const int trow = 4 * (lane >> 4), tcol = lane & 15;
+#pragma unroll
+      for (int u = 0; u < MYP; ++u) {
+        if (!pOk[u]) continue;
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int a = 16 * pI[u] + trow + q4, b = 16 * pJ[u] + tcol;
+          if (a >= PQ || b >= PQ) continue;
+          const float2 v = make_float2(accR[u][q4] * inv_n, accI[u][q4] * inv_n);
+          const int ba = a / Q, bb = b / Q, ka = a - ba * Q, kb = b - bb * Q;
+          if (ba <= bb) sS[((ba * P - ba * (ba - 1) / 2 + (bb - ba)) * Q + ka) * QS + kb] = v;
+          if (bb <= ba) sS[((bb * P - bb * (bb - 1) / 2 + (ba - bb)) * Q + kb) * QS + ka] = cconj(v);
+        }
+      }
+    }
+    block_sync();
+
+    // S(i,j)[k][l] for any (i, j)
+    auto Sget = [&](int i, int j, int k, int l) -> float2 {
+      if (i <= j) return sS[((i * P - i * (i - 1) / 2 + (j - i)) * Q + k) * QS + l];
+      return cconj(sS[((j * P - j * (j - 1) / 2 + (i - j)) * Q + l) * QS + k]);
+    };
+
+    // ------------------------------------------------ a4 init, ||R||_F = ||S||_F
+    float2 A[P * P];
+    double normR2;
+    {
+      float acc[2 * P * P + 2];
+#pragma unroll
+      for (int e = 0; e < 2 * P * P + 2; ++e) acc[e] = 0.f;
+      float nr = 0.f;
+#pragma unroll
+      for (int t = 0; t < NE; ++t) {
+        const int e = tid + 256 * t;
+        if (e < QQ) {
+          const int k = e / Q, l = e - (e / Q) * Q;
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+              const float2 s = Sget(i, j, k, l);
+              acc[2 * (i * P + j)] += s.x;
+              acc[2 * (i * P + j) + 1] += s.y;
+              nr += cabs2(s);
+            }
+        }
+      }
+      normR2 = block_sumd(double(nr), redd);
+      block_sum<2 * P * P + 2>(acc, red);
+      float an = 0.f;
+#pragma unroll
+      for (int e = 0; e < P * P; ++e) {
+        A[e] = make_float2(acc[2 * e] / float(QQ), acc[2 * e + 1] / float(QQ));
+        an += cabs2(A[e]);
+      }
+      if (double(an) <= 1e-24 * normR2) {   // fallback: partial trace R vec(I_q)
+        float pt[2 * P * P + 2];
+#pragma unroll
+        for (int e = 0; e < 2 * P * P + 2; ++e) pt[e] = 0.f;
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+          const int e = tid + 256 * t;
+          if (e < QQ && e / Q == e - (e / Q) * Q) {
+            const int k = e / Q;
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+#pragma unroll
+              for (int j = 0; j < P; ++j) {
+                const float2 s = Sget(i, j, k, k);
+                pt[2 * (i * P + j)] += s.x;
+                pt[2 * (i * P + j) + 1] += s.y;
+              }
+          }
+        }
+        block_sum<2 * P * P + 2>(pt, red);
+#pragma unroll
+        for (int e = 0; e < P * P; ++e) A[e] = make_float2(pt[2 * e], pt[2 * e + 1]);
+      }
+    }
+
+    float eta = 0.f;
+    int iters = 0;
+    const bool zero = !(normR2 > 0.0);
+    const bool bad = !isfinite(normR2);
+    float2 bv[NE];
+#pragma unroll
+    for (int t = 0; t < NE; ++t) bv[t] = cz();
+    EC ua[P];
+    EC va[RAM];
+#pragma unroll
+    for (int i = 0; i < P; ++i) ua[i] = czero<EC>();
+#pragma unroll
+    for (int cc = 0; cc < RAM; ++cc) va[cc] = czero<EC>();
+
+    if (!zero && !bad) {
+      float2 Ap[P * P];
+      double resid = 0.0;
+      float anorm2 = 0.f;
+#pragma unroll
+      for (int e = 0; e < P * P; ++e) anorm2 += cabs2(A[e]);
+      auto sweep = [&](bool res) {
+        const float ainv = 1.f / anorm2;
+        float acc[2 * P * P + 2];
+#pragma unroll
+        for (int e = 0; e < 2 * P * P + 2; ++e) acc[e] = 0.f;
+        double rr = 0.0;
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+          const int e = tid + 256 * t;
+          if (e < QQ) {
+            const int k = e / Q, l = e - (e / Q) * Q;
+            // first pass over the blocks: residual of the previous iterate and
+            // the new b; second pass (S re-read): partial sums of R conj(b)
+            float a2 = 0.f;
+            float2 bn = cz();
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+#pragma unroll
+              for (int j = 0; j < P; ++j) {
+                const float2 sv = Sget(i, j, k, l);
+                if (res) a2 += cabs2(csub(sv, cmul(A[i * P + j], bv[t])));
+                bn = ccfma(A[i * P + j], sv, bn);
+              }
+            if (res) rr += double(a2);
+            bn = cscale(bn, ainv);
+            bv[t] = bn;
+            acc[2 * P * P] += cabs2(bn);
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+#pragma unroll
+              for (int j = 0; j < P; ++j) {
+                const float2 pa = ccfma(bn, Sget(i, j, k, l), cz());
+                acc[2 * (i * P + j)] += pa.x;
+                acc[2 * (i * P + j) + 1] += pa.y;
+              }
+          } else {
+            bv[t] = cz();
+          }
+        }
+        block_sum<2 * P * P + 2>(acc, red);
+        const float binv = 1.f / acc[2 * P * P];
+#pragma unroll
+        for (int ij = 0; ij < P * P; ++ij) Ap[ij] = make_float2(acc[2 * ij] * binv, acc[2 * ij + 1] * binv);
+        if (res) resid = block_sumd(rr, redd);
+      };
+      auto eig_a = [&](bool cold) {
+        EC Ah[P * P];
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+          for (int j = 0; j < P; ++j)
+            Ah[i * P + j] = cscale(cadd(cto<EC>(Ap[i * P + j]), cconj(cto<EC>(Ap[j * P + i]))), ES(0.5));
+        if (r_a == 1) {
+          power_top<P, EC>(Ah, ua, cold, 500, PREC ? 1e-12 : 2e-6);
+          ES lam = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            EC s = czero<EC>();
+#pragma unroll
+            for (int j = 0; j < P; ++j) s = cfma(Ah[i * P + j], ua[j], s);
+            lam += ua[i].x * s.x + ua[i].y * s.y;
+          }
+          anorm2 = 0.f;
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+              A[i * P + j] = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
+              anorm2 += cabs2(A[i * P + j]);
+            }
+          return;
+        }
+        block_sync();
+        if (tid == 0) {
+#pragma unroll
+          for (int e = 0; e < P * P; ++e) {
+            sA[e] = tof(Ah[e]);
+            sAh[e] = Ah[e];
+          }
+        }
+        block_sync();
+        float2 mrow[P];
+#pragma unroll
+        for (int j = 0; j < P; ++j) mrow[j] = sA[(lane < P ? lane : 0) * P + j];
+        group_subspace<RAM, 64, P, EC>(mrow, lane < P, r_a, va, sVa, cold, 500, PREC ? 1e-12 : 2e-6);
+        block_sync();
+        if (wave == 0 && lane < P) {
+#pragma unroll
+          for (int cc = 0; cc < RAM; ++cc)
+            if (cc < r_a) sUA[lane * RAM + cc] = va[cc];
+        }
+        block_sync();
+        EC Hs[RAM][RAM];
+#pragma unroll
+        for (int a = 0; a < RAM; ++a)
+#pragma unroll
+          for (int b = 0; b < RAM; ++b) {
+            EC s = czero<EC>();
+            if (a < r_a && b < r_a) {
+              for (int i = 0; i < P; ++i) {
+                EC t2 = czero<EC>();
+                for (int j = 0; j < P; ++j) t2 = cfma(sAh[i * P + j], sUA[j * RAM + b], t2);
+                s = ccfma(sUA[i * RAM + a], t2, s);
+              }
+            }
+            Hs[a][b] = s;
+          }
+        anorm2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            EC s = czero<EC>();
+#pragma unroll
+            for (int a = 0; a < RAM; ++a) {
+              if (a >= r_a) continue;
+              EC t2 = czero<EC>();
+#pragma unroll
+              for (int b = 0; b < RAM; ++b)
+                if (b < r_a) t2 = cfma(Hs[a][b], cconj(sUA[j * RAM + b]), t2);
+              s = cfma(sUA[i * RAM + a], t2, s);
+            }
+            A[i * P + j] = tof(s);
+            anorm2 += cabs2(A[i * P + j]);
+          }
+        block_sync();
+      };
+      sweep(false);
+      eig_a(true);
+      iters = 1;
+      double eta_prev = INFINITY;
+      while (true) {
+        sweep(true);
+        const double e = sqrt(resid / normR2);
+        eta = float(e);
+        const bool stop = iters >= prm.max_iter ||
+                          (prm.eps > 0.0 && iters >= prm.min_iter && fabs(e - eta_prev) <= prm.eps);
+        if (stop) break;
+        eta_prev = e;
+        eig_a(false);
+        ++iters;
+      }
+    }
+    // U_A of this pixel (rows of the r_a = 1 power iterate, or the subspace)
+    block_sync();
+    if (tid == 0 && r_a == 1) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) sUA[i * RAM] = ua[i];
+    }
+    // raw B to LDS (S is dead)
+#pragma unroll
+    for (int t = 0; t < NE; ++t) {
+      const int e = tid + 256 * t;
+      if (e < QQ) sS[e] = bv[t];
+    }
+    block_sync();
+    // ---------------------------------------------- a6 + a8, every wave alike
+    const bool rok = lane < Q;
+    float2 Bq[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l)
+      Bq[l] = rok ? cscale(cadd(sS[lane * Q + l], cconj(sS[l * Q + lane])), 0.5f) : cz();
+    block_sync();
+    const bool use = rok && !zero && !bad;
+    EC vb[RBM];
+#pragma unroll
+    for (int cc = 0; cc < RBM; ++cc) vb[cc] = czero<EC>();
+    if (r_b > 0)
+      group_subspace<RBM, QP, Q, EC>(Bq, use, r_b, vb, reinterpret_cast<EC*>(sS) + QQ, true, 200,
+                                     PREC ? 1e-12 : 2e-6);
+    const EC bsk = use ? cto<EC>(prm.b_s[lane]) : czero<EC>();
+    EC gk = bsk;
+    if (r_b > 0) {
+#pragma unroll
+      for (int cc = 0; cc < RBM; ++cc) {
+        if (cc >= r_b) continue;
+        const EC coef = gsum<QP>(ccfma(vb[cc], bsk, czero<EC>()));
+        if (use) gk = csub(gk, cmul(vb[cc], coef));
+      }
+    }
+    EC w[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const EC xv = use ? cto<EC>(xp[int64_t(i) * H * W * Q + lane]) : czero<EC>();
+      w[i] = gsum<QP>(cmul(xv, cconj(gk)));
+    }
+    const ES den = gsum<QP>(ES(bsk.x * gk.x + bsk.y * gk.y));
+    EC z[P];
+    {
+      EC cw[RAM];
+#pragma unroll
+      for (int cc = 0; cc < RAM; ++cc) {
+        cw[cc] = czero<EC>();
+        if (cc < r_a) {
+#pragma unroll
+          for (int i = 0; i < P; ++i) cw[cc] = ccfma(sUA[i * RAM + cc], w[i], cw[cc]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        z[i] = w[i];
+#pragma unroll
+        for (int cc = 0; cc < RAM; ++cc)
+          if (cc < r_a) z[i] = csub(z[i], cmul(sUA[i * RAM + cc], cw[cc]));
+      }
+    }
+    const bool den_ok = den > ES(1e-12) * ES(prm.bs_norm2);
+    float T;
+    if (prm.stat_mode == 0) {
+      ES num = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) num += cabs2(z[i]);
+      T = den_ok ? float(num / den) : 0.f;
+    } else {
+      EC hz = czero<EC>(), fh[P], hs[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) fh[i] = hs[i] = cto<EC>(prm.h_s[i]);
+#pragma unroll
+      for (int cc = 0; cc < RAM; ++cc) {
+        if (cc >= r_a) continue;
+        EC chh = czero<EC>();
+#pragma unroll
+        for (int i = 0; i < P; ++i) chh = ccfma(sUA[i * RAM + cc], hs[i], chh);
+#pragma unroll
+        for (int i = 0; i < P; ++i) fh[i] = csub(fh[i], cmul(sUA[i * RAM + cc], chh));
+      }
+      ES hfh = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        hz = ccfma(hs[i], z[i], hz);
+        hfh += hs[i].x * fh[i].x + hs[i].y * fh[i].y;
+      }
+      const bool ok = den_ok && hfh > ES(1e-12) * ES(prm.h_norm2);
+      T = ok ? float(cabs2(hz) / (hfh * den)) : 0.f;
+    }
+    if (!isfinite(T)) T = NAN;
+    if (zero) T = 0.f;
+    if (bad) T = NAN;
+    if (tid == 0) {
+      prm.T[idx] = T;
+      if (MODE == kModeRun && prm.D) prm.D[idx] = (T > prm.tau) ? 1 : 0;
+      if (MODE == kModeProbe) {
+        if (prm.eta) prm.eta[idx] = eta;
+        if (prm.iters) prm.iters[idx] = iters;
+      }
+    }
+    if (MODE == kModeProbe && wave == 0) {
+      if (prm.UA && lane < P) {
+#pragma unroll
+        for (int cc = 0; cc < RAM; ++cc)
+          if (cc < r_a) prm.UA[(idx * P + lane) * r_a + cc] = (zero || bad) ? cz() : tof(sUA[lane * RAM + cc]);
+      }
+      if (prm.UB && lane < Q) {
+#pragma unroll
+        for (int cc = 0; cc < RBM; ++cc)
+          if (cc < r_b) prm.UB[(idx * Q + lane) * r_b + cc] = (zero || bad) ? cz() : tof(vb[cc]);
+      }
+    }
+    block_sync();
+  }
+}
+
+template <int P, int Q, int RBM, int MODE, int PREC>
+__global__ __launch_bounds__(256, 1) void kstap_wide_kernel(const KParams prm) {
+  __shared__ __attribute__((aligned(16))) char lds[WideLds<P, Q, RBM, PREC>::bytes];
+  int64_t first, count;
+  if (MODE == kModeRun) {
+    const int per = gridDim.x >> 3;
+    const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    if (logical >= prm.nlogical) return;
+    const int64_t total = int64_t(prm.H) * prm.W;
+    first = int64_t(logical) * prm.pix_per_block;
+    count = total - first;
+    if (count > prm.pix_per_block) count = prm.pix_per_block;
+  } else {
+    first = int64_t(blockIdx.x) * prm.pix_per_block;
+    count = prm.npix - first;
+    if (count > prm.pix_per_block) count = prm.pix_per_block;
+  }
+  run_pixels_wide<P, Q, RBM, MODE, PREC>(prm, first, count, lds);
+}
+
 __global__ void reset_counters(unsigned long long* c, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
 }
@@ -1134,6 +1767,20 @@ int launch_one(int mode, const KParams& prm, hipStream_t stream) {
     hipLaunchKernelGGL((kstap_kernel<P, Q, RBM, kModeRun, PREC>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
   else
     hipLaunchKernelGGL((kstap_kernel<P, Q, RBM, kModeProbe, PREC>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
+  return hipGetLastError();
+}
+
+template <int P, int Q, int RBM, int PREC>
+int launch_wide(int mode, const KParams& prm, hipStream_t stream) {
+  int64_t units = (mode == kModeRun) ? int64_t(prm.nlogical) : (int64_t(prm.npix) + prm.pix_per_block - 1) / prm.pix_per_block;
+  if (units <= 0) return hipSuccess;
+  int64_t grid = (mode == kModeRun) ? ((units + 7) / 8) * 8 : units;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  if (mode == kModeRun)
+    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeRun, PREC>), dim3(unsigned(grid)), dim3(256), 0, stream, prm);
+  else
+    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeProbe, PREC>), dim3(unsigned(grid)), dim3(256), 0, stream,
+                       prm);
   return hipGetLastError();
 }
 
@@ -1162,6 +1809,11 @@ const Entry kTable[] = {
     KSTAP_ENTRY(6, 8, 4, 0),
     KSTAP_ENTRY(3, 8, 4, 1),  KSTAP_ENTRY(3, 8, 8, 1),  KSTAP_ENTRY(3, 12, 4, 1), KSTAP_ENTRY(3, 12, 8, 1),
     KSTAP_ENTRY(3, 16, 4, 1), KSTAP_ENTRY(3, 16, 8, 1),
+    // wide pixels: one 4-wave workgroup per pixel (no persistent form)
+    {5, 24, 4, 0, &launch_wide<5, 24, 4, 0>, nullptr, nullptr},
+    {5, 24, 4, 1, &launch_wide<5, 24, 4, 1>, nullptr, nullptr},
+    {6, 16, 4, 0, &launch_wide<6, 16, 4, 0>, nullptr, nullptr},
+    {6, 16, 4, 1, &launch_wide<6, 16, 4, 1>, nullptr, nullptr},
 };
 #undef KSTAP_ENTRY
 
@@ -1184,12 +1836,12 @@ int launch_pixels(int p, int q, int precision, int mode, const KParams& prm, hip
 
 int kernel_class(int p, int q, int r_b, int precision) {
   const Entry* e = find(p, q, r_b, precision);
-  return e ? int(e - kTable) : -1;
+  return (e && e->persist) ? int(e - kTable) : -1;
 }
 
 int launch_persistent(int cls, const KParams* descs, const int32_t* order, const int64_t* prefix, int nt, int ppb,
                       unsigned long long* counter, int grid, hipStream_t stream) {
-  if (cls < 0 || cls >= int(sizeof(kTable) / sizeof(kTable[0]))) return hipErrorInvalidValue;
+  if (cls < 0 || cls >= int(sizeof(kTable) / sizeof(kTable[0])) || !kTable[cls].persist) return hipErrorInvalidValue;
   return kTable[cls].persist(descs, order, prefix, nt, ppb, counter, grid, stream);
 }
 

@@ -185,3 +185,78 @@ def white_noise(shape, seed: int) -> np.ndarray:
     """Seeded CN(0, 1) samples, complex128."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / np.sqrt(2.0)
+
+
+def make_scene_torch(spec: SceneSpec, seed: int = BASE_SEED, device="cuda"):
+    """The same scene model drawn on a device with torch (for large benchmark
+    workloads): factor pairs and targets from NumPy's PCG64 as in make_scene,
+    per-pixel Gaussian draws from a seeded torch generator on `device`.
+    Returns a complex64 torch tensor [p][H][W][q] (different draws than
+    make_scene for the same seed)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p, q, H, W = spec.p, spec.q, spec.H, spec.W
+    pq = p * q
+    pairs, blk, nby, nbx = _factor_pairs(spec, rng)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    x = torch.empty((p, H, W, q), dtype=torch.complex64, device=device)
+    for by in range(nby):
+        for bx in range(nbx):
+            a, b = pairs[(by, bx)]
+            cov = np.kron(a, b) + np.eye(pq)
+            lam, v = np.linalg.eigh(cov)
+            root = (v * np.sqrt(np.clip(lam, 0.0, None))) @ v.conj().T
+            r0, r1 = by * blk, min(H, (by + 1) * blk)
+            c0, c1 = bx * blk, min(W, (bx + 1) * blk)
+            npx = (r1 - r0) * (c1 - c0)
+            w = torch.complex(torch.randn((npx, pq), generator=gen, device=device),
+                              torch.randn((npx, pq), generator=gen, device=device)) * (1.0 / np.sqrt(2.0))
+            rt = torch.from_numpy(root.T.astype(np.complex64)).to(device)
+            snap = (w @ rt).reshape(r1 - r0, c1 - c0, p, q)
+            x[:, r0:r1, c0:c1, :] = snap.permute(2, 0, 1, 3)
+    nt = spec.n_targets
+    rows = rng.integers(0, H, nt)
+    cols = rng.integers(0, W, nt)
+    snr = rng.uniform(*spec.snr_db, nt) if isinstance(spec.snr_db, tuple) else np.full(nt, float(spec.snr_db))
+    theta = rng.uniform(0.0, 2.0 * np.pi, nt)
+    phase = rng.uniform(0.0, 2.0 * np.pi, nt)
+    bs = np.ones(q, dtype=np.complex128) if spec.b_steer is None else np.asarray(spec.b_steer, np.complex128)
+    for t in range(nt):
+        alpha = np.sqrt(10.0 ** (snr[t] / 10.0)) * np.exp(1j * phase[t])
+        tgt = alpha * np.outer(np.exp(1j * theta[t] * np.arange(p)), bs)
+        x[:, rows[t], cols[t], :] += torch.from_numpy(tgt.astype(np.complex64)).to(device)
+    return x
+
+
+def batch_tile_specs(seed: int = BASE_SEED + 3, ntiles: int = 64):
+    """Uneven tiles: side in {128, 256, 512, 1024}, q in {8, 12, 16},
+    n in {64, 128, 256}, p = 3, rank(A) in {1, 2}, rank(B) in {2..6};
+    targets = max(1, round(area * 200 / 2048^2)).  Returns a list of
+    (SceneSpec, n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(ntiles):
+        side = int(rng.choice([128, 256, 512, 1024]))
+        q = int(rng.choice([8, 12, 16]))
+        n = int(rng.choice([64, 128, 256]))
+        ra = int(rng.integers(1, 3))
+        rb = int(rng.integers(2, 7))
+        nt = max(1, int(round(side * side * 200 / 2048 ** 2)))
+        out.append((SceneSpec(p=3, q=q, H=side, W=side, r_a=ra, r_b=rb, n_targets=nt, snr_db=(0.0, 15.0)), n))
+    return out
+
+
+def serving_trace(seed: int = BASE_SEED + 4, nframes: int = 300):
+    """Frame requests: square side ~ U{256..2048}, q in {8, 16},
+    n ~ U{64..256}, p = 3, rank(A) = 1, rank(B) = 3, targets at 200 per
+    2048^2 pixels.  Returns a list of (SceneSpec, n)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for _ in range(nframes):
+        side = int(rng.integers(256, 2049))
+        q = int(rng.choice([8, 16]))
+        n = int(rng.integers(64, 257))
+        nt = max(1, int(round(side * side * 200 / 2048 ** 2)))
+        out.append((SceneSpec(p=3, q=q, H=side, W=side, r_a=1, r_b=3, n_targets=nt, snr_db=(0.0, 15.0)), n))
+    return out

@@ -308,3 +308,36 @@ def test_mixed_precision_parity(case):
     note(f"[bf16x3 {case}] per-output max error over {int(g.sum())} graded px: T {eT[g].max():.2e}, "
          f"P_A {dA[g].max():.2e}, P_B {dB[g].max():.2e}, eta(rel) {eeta[g].max():.2e}, iters diff {it[g].max()}")
     assert eT[g].max() <= TOL and dA[g].max() <= 1e-4 and dB[g].max() <= 1e-4
+
+
+# ------------------------------------------------------------- wide pixels
+@pytest.mark.parametrize("case", ["p5q24_fp32", "p5q24_bf16x3", "p6q16_ra2_fp32", "p6q16_ra2_bf16x3"])
+def test_wide_pixel_parity(case):
+    """p*q > 64 (one 4-wave workgroup per pixel): p=5, q=24, n=256 (the
+    mixed-precision workload's shape) and p=6, q=16, r_a=2 (two stacked
+    3-channel passes)."""
+    kstap = _kstap()
+    prec = "bf16x3" if case.endswith("bf16x3") else "fp32"
+    if case.startswith("p5"):
+        spec = scenegen.SceneSpec(p=5, q=24, H=42, W=40, r_a=1, r_b=4, n_targets=4, snr_db=(0.0, 15.0), block=20)
+        base = dict(p=5, q=24, n=256, r_a=1, r_b=4)
+    else:
+        spec = scenegen.SceneSpec(p=6, q=16, H=36, W=40, r_a=2, r_b=3, n_targets=4)
+        base = dict(p=6, q=16, n=200, r_a=2, r_b=3)
+    sc = scenegen.make_scene(spec, seed=scenegen.BASE_SEED + 70 + len(case))
+    plan = kstap.Plan(**base, precision=prec)
+    note(f"wide {case}")
+    Tg, Dg, xd = run_frame(plan, sc.x)
+    ref, out = frame_oracle(sc.x, oracle.OracleConfig(**base))
+    check_parity(Tg.ravel(), Dg.ravel(), ref, plan.tau, base["r_a"], base["r_b"], "wide " + case)
+    pix = out["pixels"][::7]
+    pr = kstap.probe(plan, xd, pix)
+    torch.cuda.synchronize()
+    sel = np.arange(0, len(out["pixels"]), 7)
+    UB = pr["U_B"].cpu().numpy().astype(np.complex128)
+    dB = np.abs(UB @ np.conj(np.swapaxes(UB, 1, 2)) - out["U_B"][sel] @ np.conj(np.swapaxes(out["U_B"][sel], 1, 2))).max()
+    UA = pr["U_A"].cpu().numpy().astype(np.complex128)
+    dA = np.abs(UA @ np.conj(np.swapaxes(UA, 1, 2)) - out["U_A"][sel] @ np.conj(np.swapaxes(out["U_A"][sel], 1, 2))).max()
+    np.testing.assert_array_equal(pr["T"].cpu().numpy(), Tg[pix[:, 0], pix[:, 1]])
+    note(f"[wide {case}] probe projector distance A {dA:.2e} B {dB:.2e}")
+    assert dA <= 1e-4 and dB <= 1e-4
