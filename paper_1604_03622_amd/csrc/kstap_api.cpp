@@ -345,7 +345,7 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
   fill_params(plan, x, H, W, &k);
   k.T = T;
   k.D = D;
-  const int64_t total = int64_t(H) * W;
+  const int64_t total = kstap::tiled_positions(H, W);
   // enough workgroups to cover 256 CUs several times over, at most 16 pixels each
   int64_t ppb = total / (256 * 8 * 4);
   ppb = std::max<int64_t>(1, std::min<int64_t>(16, ppb));
@@ -414,7 +414,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
     k.T = tl.T;
     k.D = tl.D;
     k.range_first = 0;
-    k.range_end = int64_t(tl.H) * tl.W;
+    k.range_end = kstap::tiled_positions(tl.H, tl.W);
     b->descs.push_back(k);
     b->pixels += int64_t(tl.H) * tl.W;
     const double pq = double(c.p) * c.q;

@@ -28,9 +28,9 @@ struct KParams {
   float bs_norm2;         // ||b_s||^2
   float h_norm2;          // ||h||^2
   int32_t r0, r1, c0, c1; // valid region, half-open
-  int32_t pix_per_block;  // run: consecutive row-major pixels per workgroup
+  int32_t pix_per_block;  // run: consecutive tiled-order positions per workgroup
   int32_t nlogical;       // run: workgroups that carry pixels (grid is rounded up to 8)
-  int64_t range_first;    // persistent: row-major pixel range [range_first, range_end) of the frame
+  int64_t range_first;    // persistent: tiled-order position range [range_first, range_end)
   int64_t range_end;
   // probe
   const int32_t* pix;     // [npix][2]
@@ -45,6 +45,38 @@ struct KParams {
 };
 
 enum Mode { kModeRun = 0, kModeProbe = 1 };
+
+// Tiled visiting order of a frame's pixels.  The frame is cut into 4 x 4
+// pixel units; units are grouped into horizontal stripes 16 units (64 pixels)
+// high and, inside a stripe, taken column of units by column of units, top to
+// bottom.  Position pos = 16 * unit + 4 * (row in unit) + (column in unit).
+// A run of consecutive positions therefore covers a compact patch of the
+// frame, so the training windows of the workgroups that are in flight on one
+// XCD at the same time overlap and their snapshots are served from its L2
+// instead of being fetched again.  Positions past the right or bottom edge
+// of the frame map to no pixel.
+constexpr int kUnit = 4;
+constexpr int kStripeUnits = 16;
+
+__host__ __device__ inline int64_t tiled_positions(int H, int W) {
+  const int64_t nbr = (H + kUnit - 1) / kUnit, nbc = (W + kUnit - 1) / kUnit;
+  return nbr * nbc * (kUnit * kUnit);
+}
+
+// Pixel (r, c) at position pos; false if the position lies outside the frame.
+__host__ __device__ inline bool tiled_pixel(int64_t pos, int H, int W, int* r, int* c) {
+  const int nbr = (H + kUnit - 1) / kUnit, nbc = (W + kUnit - 1) / kUnit;
+  const int64_t u = pos / (kUnit * kUnit);
+  const int k = int(pos - u * (kUnit * kUnit));
+  const int64_t per_stripe = int64_t(kStripeUnits) * nbc;
+  const int s = int(u / per_stripe);
+  const int within = int(u - int64_t(s) * per_stripe);
+  const int rows = (nbr - kStripeUnits * s < kStripeUnits) ? nbr - kStripeUnits * s : kStripeUnits;
+  const int cb = within / rows, rb = within - cb * rows;
+  *r = (kStripeUnits * s + rb) * kUnit + k / kUnit;
+  *c = cb * kUnit + k % kUnit;
+  return *r < H && *c < W;
+}
 
 // Returns true if a kernel is built for (p, q, r_b bound, precision).
 bool kernel_available(int p, int q, int r_b, int precision);

@@ -329,6 +329,18 @@ __device__ __forceinline__ void power_top(const C (&M)[P * P], C (&u)[P], bool c
   }
 }
 
+// Training-vector load.  Lanes whose element does not exist (rows past p*q,
+// vectors past n) read a zero from kZeroVec instead of taking a branch, so
+// every load is issued unconditionally and its value is used as loaded.
+// Without branches around the loads the compiler counts the loads in flight
+// exactly and waits only for the ones an MFMA is about to consume, which
+// keeps the prefetch ring full.
+__device__ float2 kZeroVec[1];   // never written
+__device__ __forceinline__ float2 load_or_zero(const float2* p, bool keep) {
+  const float2* a = keep ? p : kZeroVec;
+  return *a;
+}
+
 // ------------------------------------------------------------ a2, FP32
 // S = (1/n) sum_m x_m x_m^H of one pixel on v_mfma_f32_16x16x4_f32, written
 // to LDS as the full Hermitian pq x pq matrix (row-major).
@@ -357,58 +369,72 @@ __device__ __forceinline__ void scm_fp32(const float2* __restrict__ xp, const in
       const bool mok = m < n;
       const int off = sOff[mok ? m : 0];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) v[I] = (mok && row_ok[I]) ? xp[chan_off[I] + off] : cz();
+      for (int I = 0; I < NB; ++I) v[I] = load_or_zero(xp + chan_off[I] + off, mok && row_ok[I]);
+    };
+    // MFMAs of one 4-vector chunk
+    auto accumulate = [&](const float2 (&v)[NB]) {
+      float xr[NB], xi[NB], nxr[NB];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        xr[I] = v[I].x;
+        xi[I] = v[I].y;
+        nxr[I] = -v[I].x;
+      }
+      // first product of every accumulator, then the second: no two
+      // consecutive MFMAs write the same accumulator
+      {
+        int t = 0, u = 0;
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+          for (int J = I; J < NB; ++J) {
+            accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[I], xr[J], accR[t], 0, 0, 0);
+            if (J > I) {
+              accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[J], accI[u], 0, 0, 0);
+              ++u;
+            } else {
+              accD[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[I], accD[I], 0, 0, 0);
+            }
+            ++t;
+          }
+      }
+      {
+        int t = 0, u = 0;
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+          for (int J = I; J < NB; ++J) {
+            accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xi[J], accR[t], 0, 0, 0);
+            if (J > I) {
+              accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(nxr[I], xi[J], accI[u], 0, 0, 0);
+              ++u;
+            }
+            ++t;
+          }
+      }
     };
 #pragma unroll
-    for (int s0 = 0; s0 < PF - 1; ++s0) fetch(s0, ring[s0]);
-    for (int ch0 = 0; ch0 < nch; ch0 += PF) {
+    for (int s0 = 0; s0 < PF - 1; ++s0) {   // in order: oldest chunk's loads first
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(s0, ring[s0]);
+    }
+    // whole groups of PF chunks: branch-free, so the loads of the ring are
+    // waited for one chunk at a time (fetches past n read zeros)
+    int ch0 = 0;
+    for (; ch0 + PF <= nch; ch0 += PF) {
 #pragma unroll
       for (int sl = 0; sl < PF; ++sl) {
-        const int ch = ch0 + sl;
-        fetch(ch + PF - 1, ring[(sl + PF - 1) % PF]);
-        if (ch < nch) {
-          float xr[NB], xi[NB], nxr[NB];
-#pragma unroll
-          for (int I = 0; I < NB; ++I) {
-            xr[I] = ring[sl][I].x;
-            xi[I] = ring[sl][I].y;
-            nxr[I] = -ring[sl][I].x;
-          }
-          // first product of every accumulator, then the second: no two
-          // consecutive MFMAs write the same accumulator
-          {
-            int t = 0, u = 0;
-#pragma unroll
-            for (int I = 0; I < NB; ++I)
-#pragma unroll
-              for (int J = I; J < NB; ++J) {
-                accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[I], xr[J], accR[t], 0, 0, 0);
-                if (J > I) {
-                  accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[J], accI[u], 0, 0, 0);
-                  ++u;
-                } else {
-                  accD[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xr[I], accD[I], 0, 0, 0);
-                }
-                ++t;
-              }
-          }
-          {
-            int t = 0, u = 0;
-#pragma unroll
-            for (int I = 0; I < NB; ++I)
-#pragma unroll
-              for (int J = I; J < NB; ++J) {
-                accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xi[I], xi[J], accR[t], 0, 0, 0);
-                if (J > I) {
-                  accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(nxr[I], xi[J], accI[u], 0, 0, 0);
-                  ++u;
-                }
-                ++t;
-              }
-          }
-        }
+        // keep each chunk's instructions in place: hoisting work on a slot
+        // that was just fetched would wait for its load right away
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(ch0 + sl + PF - 1, ring[(sl + PF - 1) % PF]);
+        accumulate(ring[sl]);
       }
     }
+    // the last nch - ch0 < PF chunks are already in ring slots 0, 1, ...
+#pragma unroll
+    for (int sl = 0; sl < PF - 1; ++sl)
+      if (ch0 + sl < nch) accumulate(ring[sl]);
 
     // S to LDS, full Hermitian, scaled by 1/n.  MFMA output layout: lane l,
     // register q holds row 4*(l/16) + q, column l % 16 of the 16 x 16 tile.
@@ -511,59 +537,69 @@ __device__ __forceinline__ void scm_bf16x3(const float2* __restrict__ xp, const 
       const bool mok = m < n;
       const int off = sOff[mok ? m : 0];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) v[I][e] = (mok && row_ok[I]) ? xp[chan_off[I] + off] : cz();
+      for (int I = 0; I < NB; ++I) v[I][e] = load_or_zero(xp + chan_off[I] + off, mok && row_ok[I]);
     }
   };
+  // MFMAs of one 16-vector chunk
+  auto accumulate = [&](const float2 (&v)[NB][4]) {
+    bf8 hi[NB], lo[NB];
 #pragma unroll
-  for (int s0 = 0; s0 < PF - 1; ++s0) fetch(s0, ring[s0]);
-  for (int ch0 = 0; ch0 < nch; ch0 += PF) {
+    for (int I = 0; I < NB; ++I) split_bf16(v[I], hi[I], lo[I]);
+    {
+      int t = 0;
 #pragma unroll
-    for (int sl = 0; sl < PF; ++sl) {
-      const int ch = ch0 + sl;
-      fetch(ch + PF - 1, ring[(sl + PF - 1) % PF]);
-      if (ch < nch) {
-        bf8 hi[NB], lo[NB];
+      for (int I = 0; I < NB; ++I) {
+        const bf8 zh = swap_neg(hi[I]);
 #pragma unroll
-        for (int I = 0; I < NB; ++I) split_bf16(ring[sl][I], hi[I], lo[I]);
-        {
-          int t = 0;
-#pragma unroll
-          for (int I = 0; I < NB; ++I) {
-            const bf8 zh = swap_neg(hi[I]);
-#pragma unroll
-            for (int J = I; J < NB; ++J, ++t) {
-              accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], hi[J], accR[t], 0, 0, 0);
-              accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, hi[J], accI[t], 0, 0, 0);
-            }
-          }
-        }
-        {
-          int t = 0;
-#pragma unroll
-          for (int I = 0; I < NB; ++I) {
-            const bf8 zh = swap_neg(hi[I]);
-#pragma unroll
-            for (int J = I; J < NB; ++J, ++t) {
-              accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], lo[J], accR[t], 0, 0, 0);
-              accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, lo[J], accI[t], 0, 0, 0);
-            }
-          }
-        }
-        {
-          int t = 0;
-#pragma unroll
-          for (int I = 0; I < NB; ++I) {
-            const bf8 zl = swap_neg(lo[I]);
-#pragma unroll
-            for (int J = I; J < NB; ++J, ++t) {
-              accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[I], hi[J], accR[t], 0, 0, 0);
-              accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, hi[J], accI[t], 0, 0, 0);
-            }
-          }
+        for (int J = I; J < NB; ++J, ++t) {
+          accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], hi[J], accR[t], 0, 0, 0);
+          accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, hi[J], accI[t], 0, 0, 0);
         }
       }
     }
+    {
+      int t = 0;
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        const bf8 zh = swap_neg(hi[I]);
+#pragma unroll
+        for (int J = I; J < NB; ++J, ++t) {
+          accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], lo[J], accR[t], 0, 0, 0);
+          accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, lo[J], accI[t], 0, 0, 0);
+        }
+      }
+    }
+    {
+      int t = 0;
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        const bf8 zl = swap_neg(lo[I]);
+#pragma unroll
+        for (int J = I; J < NB; ++J, ++t) {
+          accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[I], hi[J], accR[t], 0, 0, 0);
+          accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, hi[J], accI[t], 0, 0, 0);
+        }
+      }
+    }
+  };
+#pragma unroll
+  for (int s0 = 0; s0 < PF - 1; ++s0) {
+    __builtin_amdgcn_sched_barrier(0);
+    fetch(s0, ring[s0]);
   }
+  int ch0 = 0;
+  for (; ch0 + PF <= nch; ch0 += PF) {   // branch-free body, as in scm_fp32
+#pragma unroll
+    for (int sl = 0; sl < PF; ++sl) {
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(ch0 + sl + PF - 1, ring[(sl + PF - 1) % PF]);
+      __builtin_amdgcn_sched_barrier(0);   // all loads of the next chunk go out first
+      accumulate(ring[sl]);
+    }
+  }
+#pragma unroll
+  for (int sl = 0; sl < PF - 1; ++sl)
+    if (ch0 + sl < nch) accumulate(ring[sl]);
   const float inv_n = 1.f / float(n);
   const int trow = 4 * (lane >> 4), tcol = lane & 15;
   int t = 0;
@@ -618,8 +654,8 @@ struct Lds {
   static constexpr size_t bytes = ((oQeta + sizeof(float) * G) + 15) / 16 * 16;
 };
 
-// The whole per-pixel pass for `count` pixels starting at `first`: row-major
-// pixel indices of the frame (run mode) or positions in the pixel list (probe
+// The whole per-pixel pass for `count` pixels starting at `first`: positions
+// in the tiled order of the frame (run mode) or in the pixel list (probe
 // mode).  One 64-lane workgroup; `lds` holds Lds<...>::bytes.
 template <int P, int Q, int RBM, int MODE, int PREC>
 __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, int64_t count, char* lds) {
@@ -792,12 +828,13 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   };
 
   for (int64_t it = 0; it < count; ++it) {
-    const int64_t idx = first + it;
+    int64_t idx;
     int r, c;
     if (MODE == kModeRun) {
-      r = int(idx / W);
-      c = int(idx - int64_t(r) * W);
+      if (!tiled_pixel(first + it, H, W, &r, &c)) continue;
+      idx = int64_t(r) * W + c;
     } else {
+      idx = first + it;
       r = prm.pix[2 * idx];
       c = prm.pix[2 * idx + 1];
     }
@@ -1076,7 +1113,7 @@ __global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
     const int per = gridDim.x >> 3;   // grid is a multiple of 8 (one share per XCD)
     const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (logical >= prm.nlogical) return;
-    const int64_t total = int64_t(prm.H) * prm.W;
+    const int64_t total = tiled_positions(prm.H, prm.W);
     first = int64_t(logical) * prm.pix_per_block;
     count = total - first;
     if (count > prm.pix_per_block) count = prm.pix_per_block;
@@ -1089,7 +1126,8 @@ __global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
 }
 
 // Persistent batched kernel: every workgroup pops work items (runs of `ppb`
-// consecutive pixels of one tile's range [range_first, range_end)) from a
+// consecutive tiled-order positions of one tile's range [range_first,
+// range_end)) from a
 // device counter until the queue is empty.  Items are numbered tile after tile in the order of `order` (longest
 // tiles first); prefix[j] is the first item of order[j] (prefix[nt] = total).
 template <int P, int Q, int RBM, int PREC>
@@ -1252,12 +1290,13 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
   }
 
   for (int64_t itp = 0; itp < count; ++itp) {
-    const int64_t idx = first + itp;
+    int64_t idx;
     int r, c;
     if (MODE == kModeRun) {
-      r = int(idx / W);
-      c = int(idx - int64_t(r) * W);
+      if (!tiled_pixel(first + itp, H, W, &r, &c)) continue;
+      idx = int64_t(r) * W + c;
     } else {
+      idx = first + itp;
       r = prm.pix[2 * idx];
       c = prm.pix[2 * idx + 1];
     }
@@ -1292,7 +1331,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       for (int it = 0; it < NIT; ++it) {
         const int m = ch * 16 + it_v[it];
         const bool ok = it_ok[it] && m < n;
-        pre[it] = ok ? xp[it_off[it] + sOff[ok ? m : 0]] : cz();
+        pre[it] = load_or_zero(xp + it_off[it] + sOff[ok ? m : 0], ok);
       }
     };
     auto sstore = [&](int buf) {
@@ -1740,7 +1779,7 @@ __global__ __launch_bounds__(256, 1) void kstap_wide_kernel(const KParams prm) {
     const int per = gridDim.x >> 3;
     const int logical = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
     if (logical >= prm.nlogical) return;
-    const int64_t total = int64_t(prm.H) * prm.W;
+    const int64_t total = tiled_positions(prm.H, prm.W);
     first = int64_t(logical) * prm.pix_per_block;
     count = total - first;
     if (count > prm.pix_per_block) count = prm.pix_per_block;

@@ -85,7 +85,8 @@ struct Frame {
   uint8_t* D_out = nullptr;
   int cls = -1;
   size_t off = 0, bytes = 0, x_bytes = 0;
-  int64_t cursor = 0, total = 0, inflight_end = 0;
+  int64_t cursor = 0, total = 0, inflight_end = 0;   // cursor/inflight_end/npos: tiled-order positions
+  int64_t npos = 0;
   double t_submit = 0, t_done = 0;
   int state = kPending;
   stap_status status = STAP_OK;
@@ -205,7 +206,7 @@ void stap_server_s::loop() {
         else if (e != hipErrorNotReady)
           finish(f, STAP_ERR_DEVICE, hipGetErrorString(e));
       }
-      if (f->state == kComputing && f->cursor < f->total) ready.push_back(f);
+      if (f->state == kComputing && f->cursor < f->npos) ready.push_back(f);
     }
     if (ready.empty()) {
       if (stop && pending.empty() && active.empty()) break;
@@ -227,7 +228,7 @@ void stap_server_s::loop() {
       k.T = reinterpret_cast<float*>(arena_base + f->off + xb);
       k.D = reinterpret_cast<uint8_t*>(arena_base + f->off + xb + (px * 4 + 255) / 256 * 256);
       k.range_first = f->cursor;
-      k.range_end = std::min<int64_t>(f->total, f->cursor + share);
+      k.range_end = std::min<int64_t>(f->npos, f->cursor + share);
       f->inflight_end = k.range_end;
       by_cls[f->cls].push_back(int32_t(i));
     }
@@ -290,7 +291,7 @@ void stap_server_s::loop() {
         continue;
       }
       f->cursor = f->inflight_end;
-      if (f->cursor < f->total) continue;
+      if (f->cursor < f->npos) continue;
       const size_t xb = (f->x_bytes + 255) / 256 * 256;
       const size_t px = size_t(f->H) * f->W;
       hipError_t d = hipMemcpyAsync(f->T_out, arena_base + f->off + xb, px * 4, hipMemcpyDeviceToHost, s_copy);
@@ -384,6 +385,7 @@ stap_status stap_server_submit(stap_server_t* srv, const stap_plan_t* plan, cons
   f->cls = cls;
   f->bytes = frame_bytes(plan, H, W, f->x_on_device, &f->x_bytes);
   f->total = int64_t(H) * W;
+  f->npos = kstap::tiled_positions(H, W);
   if (f->bytes > srv->budget) {
     delete f;
     return fail(STAP_ERR_BUSY, "frame needs %zu bytes of device memory, the budget is %zu", size_t(f->bytes),
