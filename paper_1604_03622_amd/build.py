@@ -17,7 +17,8 @@ BUILD = os.path.join(PKG, "_build")
 ARCH = os.environ.get("KSTAP_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kstap_kernels.hip", "kstap_api.cpp", "kstap_host.cpp", "kstap_server.cpp"]
+SOURCES = ["kstap_kern_fp32.hip", "kstap_kern_bf16.hip", "kstap_kern_wide.hip", "kstap_dispatch.hip",
+           "kstap_api.cpp", "kstap_host.cpp", "kstap_server.cpp"]
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -39,6 +39,64 @@ int device_cus() {
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, int>> g_tune_cache;   // signature -> (ppb, grid multiplier)
 
+// Split planes of the mixed path for stap_run / stap_probe come from a
+// stream-ordered pool per device that keeps its memory between calls
+// (release threshold = max), so repeated runs allocate nothing new and runs
+// on different streams never share a buffer.
+std::mutex g_pool_mu;
+std::map<int, hipMemPool_t> g_pools;
+
+hipError_t planes_pool(hipMemPool_t* out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pools.find(dev);
+  if (it != g_pools.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof(props));
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t pool = nullptr;
+  e = hipMemPoolCreate(&pool, &props);
+  if (e != hipSuccess) return e;
+  uint64_t keep = ~uint64_t(0);
+  e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e != hipSuccess) return e;
+  g_pools[dev] = pool;
+  *out = pool;
+  return hipSuccess;
+}
+
+// Enqueues the split of frame x into planes from the pool (k->xs); the
+// caller enqueues the kernel and then planes_release on the same stream.
+stap_status planes_acquire(const stap_plan_s* plan, const void* x, int H, int W, kstap::KParams* k, hipStream_t s) {
+  const stap_config& c = plan->cfg;
+  if (!kstap::kernel_needs_planes(c.p, c.q, c.r_b, c.precision)) return STAP_OK;
+  const int64_t n = int64_t(c.p) * H * W * c.q;
+  hipMemPool_t pool = nullptr;
+  hipError_t e = planes_pool(&pool);
+  void* xs = nullptr;
+  if (e == hipSuccess) e = hipMallocFromPoolAsync(&xs, size_t(n) * 8, pool, s);
+  if (e == hipErrorOutOfMemory) return fail(STAP_ERR_OUT_OF_MEMORY, "split planes: %lld bytes", (long long)(n * 8));
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "split planes: %s", hipGetErrorString(e));
+  const int le = kstap::launch_split(static_cast<const float2*>(x), static_cast<uint32_t*>(xs), n, s);
+  if (le != hipSuccess) {
+    hipFreeAsync(xs, s);
+    return fail(STAP_ERR_DEVICE, "split launch: %s", hipGetErrorString(hipError_t(le)));
+  }
+  k->xs = static_cast<const uint32_t*>(xs);
+  return STAP_OK;
+}
+
+void planes_release(const kstap::KParams& k, hipStream_t s) {
+  if (k.xs) hipFreeAsync(const_cast<uint32_t*>(k.xs), s);
+}
+
 }  // namespace
 
 struct stap_batch_s {
@@ -50,6 +108,13 @@ struct stap_batch_s {
   std::string signature;
   // device
   void* d_buf = nullptr;         // descs | order | prefix | counters
+  void* d_planes = nullptr;      // split planes of the mixed-path tiles
+  struct Split {
+    const float2* x;
+    uint32_t* xs;
+    int64_t n;
+  };
+  std::vector<Split> splits;
   kstap::KParams* d_descs = nullptr;
   int32_t* d_order = nullptr;
   int64_t* d_prefix = nullptr;
@@ -109,8 +174,24 @@ stap_status batch_build(stap_batch_s* b) {
   kp.sharedMemBytes = 0;
   kp.kernelParams = reset_args;
   kp.extra = nullptr;
+  // mixed-path tiles: their split kernels run first
+  std::vector<hipGraphNode_t> split_nodes;
+  for (size_t i = 0; i < b->splits.size() && e == hipSuccess; ++i) {
+    stap_batch_s::Split sp = b->splits[i];
+    void* sargs[] = {&sp.x, &sp.xs, &sp.n};
+    hipKernelNodeParams sn;
+    std::memset(&sn, 0, sizeof(sn));
+    sn.func = const_cast<void*>(kstap::split_kernel());
+    sn.gridDim = dim3(kstap::split_grid(sp.n));
+    sn.blockDim = dim3(256);
+    sn.kernelParams = sargs;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, g, nullptr, 0, &sn);
+    split_nodes.push_back(node);
+  }
   hipGraphNode_t reset_node = nullptr;
-  e = hipGraphAddKernelNode(&reset_node, g, nullptr, 0, &kp);
+  if (e == hipSuccess)
+    e = hipGraphAddKernelNode(&reset_node, g, split_nodes.empty() ? nullptr : split_nodes.data(), split_nodes.size(), &kp);
   for (size_t i = 0; i < b->classes.size() && e == hipSuccess; ++i) {
     const BatchClass& c = b->classes[i];
     const kstap::KParams* descs = b->d_descs;
@@ -148,7 +229,10 @@ stap_status batch_build(stap_batch_s* b) {
 // candidates needs no graph).
 stap_status batch_launch_direct(stap_batch_s* b, hipStream_t s) {
   const int grid = device_cus() * 8 * b->grid_mult;
-  int le = kstap::launch_reset(b->d_counters, int(b->classes.size()), s);
+  int le = hipSuccess;
+  for (size_t i = 0; i < b->splits.size() && le == hipSuccess; ++i)
+    le = kstap::launch_split(b->splits[i].x, b->splits[i].xs, b->splits[i].n, s);
+  if (le == hipSuccess) le = kstap::launch_reset(b->d_counters, int(b->classes.size()), s);
   for (size_t i = 0; i < b->classes.size() && le == hipSuccess; ++i) {
     const BatchClass& c = b->classes[i];
     le = kstap::launch_persistent(c.cls, b->d_descs, b->d_order + b->order_base[i], b->d_prefix + b->prefix_base[i],
@@ -162,6 +246,7 @@ void batch_free(stap_batch_s* b) {
   if (!b) return;
   batch_release_graph(b);
   if (b->d_buf) hipFree(b->d_buf);
+  if (b->d_planes) hipFree(b->d_planes);
   delete b;
 }
 
@@ -351,8 +436,11 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
   ppb = std::max<int64_t>(1, std::min<int64_t>(16, ppb));
   k.pix_per_block = int32_t(ppb);
   k.nlogical = int32_t((total + ppb - 1) / ppb);
-  const int e = kstap::launch_pixels(plan->cfg.p, plan->cfg.q, plan->cfg.precision, kstap::kModeRun, k,
-                                     static_cast<hipStream_t>(hip_stream));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  st = planes_acquire(plan, x, H, W, &k, s);
+  if (st != STAP_OK) return st;
+  const int e = kstap::launch_pixels(plan->cfg.p, plan->cfg.q, plan->cfg.precision, kstap::kModeRun, k, s);
+  planes_release(k, s);
   if (e != hipSuccess)
     return fail(STAP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
   return ok();
@@ -376,8 +464,11 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
   k.eta = out->eta;
   k.iters = out->iters;
   k.pix_per_block = 1;
-  const int e = kstap::launch_pixels(plan->cfg.p, plan->cfg.q, plan->cfg.precision, kstap::kModeProbe, k,
-                                     static_cast<hipStream_t>(hip_stream));
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  st = planes_acquire(plan, x, H, W, &k, s);
+  if (st != STAP_OK) return st;
+  const int e = kstap::launch_pixels(plan->cfg.p, plan->cfg.q, plan->cfg.precision, kstap::kModeProbe, k, s);
+  planes_release(k, s);
   if (e != hipSuccess)
     return fail(STAP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
   return ok();
@@ -427,6 +518,31 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
       it = cls_index.find(cls);
     }
     b->classes[it->second].order.push_back(t);
+  }
+  // split planes of the mixed-path tiles, in one allocation
+  std::vector<std::pair<int, int64_t>> need;   // tile, samples
+  int64_t plane_samples = 0;
+  for (int t = 0; t < ntiles; ++t) {
+    const stap_config& c = tiles[t].plan->cfg;
+    if (!kstap::kernel_needs_planes(c.p, c.q, c.r_b, c.precision)) continue;
+    const int64_t n = int64_t(c.p) * tiles[t].H * tiles[t].W * c.q;
+    need.push_back({t, n});
+    plane_samples += (n + 63) / 64 * 64;
+  }
+  if (plane_samples > 0) {
+    hipError_t pe = hipMalloc(&b->d_planes, size_t(plane_samples) * 8);
+    if (pe != hipSuccess) {
+      b->d_planes = nullptr;
+      batch_free(b);
+      return fail(STAP_ERR_OUT_OF_MEMORY, "split planes (%lld bytes): %s", (long long)(plane_samples * 8),
+                  hipGetErrorString(pe));
+    }
+    uint32_t* at = static_cast<uint32_t*>(b->d_planes);
+    for (const auto& nt : need) {
+      b->descs[nt.first].xs = at;
+      b->splits.push_back({static_cast<const float2*>(tiles[nt.first].x), at, nt.second});
+      at += 2 * ((nt.second + 63) / 64 * 64);
+    }
   }
   char sig[64];
   std::string signature;

@@ -1,17 +1,21 @@
-// Fused per-pixel Kronecker STAP kernels for gfx950 (MI355X).
+// Device code of the fused per-pixel Kronecker STAP kernels for gfx950
+// (MI355X), shared by the translation units that instantiate them
+// (kstap_kern_fp32.hip, kstap_kern_bf16.hip, kstap_kern_wide.hip).
 //
-// One 64-lane wavefront (one workgroup) carries one pixel at a time through
-// the whole pass; a workgroup walks a run of consecutive pixels of a row.
+// Narrow pixels (p*q <= 64): one 64-lane wavefront (one workgroup) carries
+// one pixel at a time through the whole pass and walks a run of positions of
+// the tiled pixel order.
 //
 //   a2  sample covariance S = (1/n) sum_m x_m x_m^H  (Sec. 1.1, Eq. (2)) as a
-//       dense contraction on FP32 MFMA (v_mfma_f32_16x16x4_f32).  With
-//       Y = [Re x; Im x] the real Gram has the blocks Re S = Xr Xr^T + Xi Xi^T
-//       and Im S = Xi Xr^T - Xr Xi^T; only the upper 16 x 16 tiles are formed,
-//       and the diagonal tiles of Im S use one product and its transpose.
-//       Operands come straight from global memory (neighbouring pixels of a
-//       workgroup, and the workgroups of one XCD, share them through L1/L2).
+//       dense contraction on MFMA.  FP32 path: v_mfma_f32_16x16x4_f32 with
+//       Re S = Xr Xr^T + Xi Xi^T and Im S = Xi Xr^T - Xr Xi^T over the upper
+//       16 x 16 tiles (diagonal tiles of Im S from one product and its
+//       transpose).  Mixed path: three BF16 products on pre-split planes.
+//       Training vectors are read through buffer resources straight into
+//       MFMA operands; workgroups that are in flight together on one XCD
+//       cover a compact patch, so their windows are served from its L2.
 //   a3  the rearrangement of Algorithm 1 is never materialised: block S(i,j)
-//       of S is row i*p + j... of R in address arithmetic only.
+//       of S is row i*p + j of R in address arithmetic only.
 //   a4  A_0 = block sums of S / q^2 (Sec. 4, Eqs. (18)-(19)).
 //   a5  LR-Kron (Algorithm 2) on the LDS-resident S: one sweep over S per
 //       iteration computes the residual of the previous iterate, the new time
@@ -21,9 +25,11 @@
 //   a6  final b = R^T conj(a) / ||a||^2 and its Hermitian part are queued
 //       in registers; every 64/q' pixels (q' = q rounded up to 8, 16 or 32)
 //       one batched subspace iteration finds the top-r_b subspaces, q' lanes
-//       per pixel with group-local DPP reductions (CholQR2, residual stop).
+//       per pixel with group-local DPP reductions (CGS2, residual stop).
 //   a8  T = ||F_A X conj(F_B b_s)||^2 / (b_s^H F_B b_s) (Sec. 5, Eq. (25);
 //       Sec. 6.3, Eq. (26)); D = T > tau.
+// Wide pixels (p*q > 64): one 4-wave workgroup per pixel, see below.
+#pragma once
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -341,12 +347,31 @@ __device__ __forceinline__ float2 load_or_zero(const float2* p, bool keep) {
   return *a;
 }
 
+// Training vectors of the narrow kernels are read through buffer resources:
+// one record per 16-row operand block, based at the pixel's window origin in
+// the channel of the block's first row.  A lane's load offset is its row
+// offset (loff) plus the stencil entry's byte offset (sOffB, in LDS).  Rows
+// past p*q and entries past n carry kOut, which lies beyond every record, so
+// the hardware returns zeros for them: no branch, select or 64-bit address
+// arithmetic per load.
+constexpr uint32_t kOut = 0x80000000u;
+constexpr int kOffPad = 64;   // sOffB entries past kMaxN (prefetch overrun, all kOut)
+
+template <int Q>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t block_rsrc(const float2* xwin, int64_t plane, uint32_t rec, int I) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(xwin + int64_t((16 * I) / Q) * plane), (short)0, int(rec),
+                                           0x00020000);
+}
+__device__ __forceinline__ float2 bload(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 // ------------------------------------------------------------ a2, FP32
 // S = (1/n) sum_m x_m x_m^H of one pixel on v_mfma_f32_16x16x4_f32, written
 // to LDS as the full Hermitian pq x pq matrix (row-major).
 template <int P, int Q>
-__device__ __forceinline__ void scm_fp32(const float2* __restrict__ xp, const int* sOff, const int (&chan_off)[(P * Q + 15) / 16],
-                                         const bool (&row_ok)[(P * Q + 15) / 16], int n, float2* sS) {
+__device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint32_t rec, const uint32_t* sOffB,
+                                         const uint32_t (&loff)[(P * Q + 15) / 16], int n, float2* sS) {
   constexpr int PQ = P * Q;
   constexpr int NB = (PQ + 15) / 16;
   constexpr int NT = NB * (NB + 1) / 2;
@@ -364,12 +389,13 @@ __device__ __forceinline__ void scm_fp32(const float2* __restrict__ xp, const in
     // operand ring: chunk ch lives in slot ch % PF; PF - 1 chunks in flight
     constexpr int PF = 4;
     float2 ring[PF][NB];
-    auto fetch = [&](int ch, float2 (&v)[NB]) {
-      const int m = ch * 4 + (lane >> 4);
-      const bool mok = m < n;
-      const int off = sOff[mok ? m : 0];
+    __amdgpu_buffer_rsrc_t rs[NB];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) v[I] = load_or_zero(xp + chan_off[I] + off, mok && row_ok[I]);
+    for (int I = 0; I < NB; ++I) rs[I] = block_rsrc<Q>(xwin, plane, rec, I);
+    auto fetch = [&](int ch, float2 (&v)[NB]) {
+      const uint32_t off = sOffB[ch * 4 + (lane >> 4)];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) v[I] = bload(rs[I], loff[I] + off);
     };
     // MFMAs of one 4-vector chunk
     auto accumulate = [&](const float2 (&v)[NB]) {
@@ -491,11 +517,16 @@ __device__ __forceinline__ void scm_fp32(const float2* __restrict__ xp, const in
 // -------------------------------------------------------- a2, split BF16
 // The same S from three BF16 products per tile: x = hi + lo with
 // hi = bf16(x), lo = bf16(x - hi); S ~ hi hi^H + hi lo^H + lo hi^H with FP32
-// accumulation on v_mfma_f32_16x16x32_bf16.  One instruction covers 16
-// training vectors: in each 16-lane group g, element 2v + part of a lane's
-// 8-element operand is (re, im) of vector 4g + v of the chunk.  Re S tiles
-// take Y_I Y_J^T with Y = (re, im) pairs; Im S tiles take Z_I Y_J^T with
-// Z = (im, -re) pairs (a half-word rotate and a sign flip of Y's bits).
+// accumulation.  The split is done once per frame by split_planes into two
+// planes in the layout of x, one packed BF16 pair (re, im) per complex
+// sample: hi first, then lo.  The covariance kernel loads MFMA operands
+// straight from them.  In a 16-vector chunk, 16-lane group g of the
+// wavefront holds vectors 4g .. 4g + 3.
+//   Re S tiles: v_mfma_f32_16x16x32_bf16 on Y = (re, im) pairs, which sums
+//     re_I re_J + im_I im_J over the 16 vectors of the chunk.
+//   Im S tiles: v_mfma_f32_16x16x16_bf16 on single components,
+//     im_I re_J^T + (-re_I) im_J^T; the operands are half-word gathers (and
+//     one sign flip) of the loaded pairs.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
@@ -517,9 +548,19 @@ __device__ __forceinline__ bf8 swap_neg(bf8 y) {
   return __builtin_bit_cast(bf8, w);
 }
 
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+
+
+
+// re (low halves) and im (high halves) of two packed pairs, as one dword
+__device__ __forceinline__ uint32_t lo_halves(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x05040100u); }
+__device__ __forceinline__ uint32_t hi_halves(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x07060302u); }
+
 template <int P, int Q>
-__device__ __forceinline__ void scm_bf16x3(const float2* __restrict__ xp, const int* sOff, const int (&chan_off)[(P * Q + 15) / 16],
-                                           const bool (&row_ok)[(P * Q + 15) / 16], int n, float2* sS) {
+__device__ __forceinline__ void scm_bf16x3(const uint32_t* hwin, const uint32_t* lwin, int64_t plane, uint32_t rec,
+                                           const uint32_t* sOffB, const uint32_t (&loff)[(P * Q + 15) / 16], int n,
+                                           float2* sS) {
   constexpr int PQ = P * Q;
   constexpr int NB = (PQ + 15) / 16;
   constexpr int NT = NB * (NB + 1) / 2;
@@ -529,58 +570,58 @@ __device__ __forceinline__ void scm_bf16x3(const float2* __restrict__ xp, const 
   for (int t = 0; t < NT; ++t) accR[t] = accI[t] = f4{0.f, 0.f, 0.f, 0.f};
   const int nch = (n + 15) >> 4;
   constexpr int PF = 2;
-  float2 ring[PF][NB][4];
-  auto fetch = [&](int ch, float2 (&v)[NB][4]) {
+  u4 ring[PF][2][NB];   // hi / lo pairs of the lane's 4 vectors, per block
+  __amdgpu_buffer_rsrc_t rh[NB], rl[NB];
+#pragma unroll
+  for (int I = 0; I < NB; ++I) {
+    const int64_t cb = int64_t((16 * I) / Q) * plane;
+    rh[I] = __builtin_amdgcn_make_buffer_rsrc((void*)(hwin + cb), (short)0, int(rec), 0x00020000);
+    rl[I] = __builtin_amdgcn_make_buffer_rsrc((void*)(lwin + cb), (short)0, int(rec), 0x00020000);
+  }
+  auto fetch = [&](int ch, u4 (&v)[2][NB]) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int m = ch * 16 + 4 * (lane >> 4) + e;
-      const bool mok = m < n;
-      const int off = sOff[mok ? m : 0];
+      const uint32_t off = sOffB[ch * 16 + 4 * (lane >> 4) + e];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) v[I][e] = load_or_zero(xp + chan_off[I] + off, mok && row_ok[I]);
+      for (int I = 0; I < NB; ++I) {
+        v[0][I][e] = __builtin_amdgcn_raw_buffer_load_b32(rh[I], loff[I] + off, 0, 0);
+        v[1][I][e] = __builtin_amdgcn_raw_buffer_load_b32(rl[I], loff[I] + off, 0, 0);
+      }
     }
   };
   // MFMAs of one 16-vector chunk
-  auto accumulate = [&](const float2 (&v)[NB][4]) {
-    bf8 hi[NB], lo[NB];
+  auto accumulate = [&](const u4 (&v)[2][NB]) {
+    bf8 yh[NB], yl[NB];
+    s4 reh[NB], rel[NB], imh[NB], iml[NB], nreh[NB], nrel[NB];
 #pragma unroll
-    for (int I = 0; I < NB; ++I) split_bf16(v[I], hi[I], lo[I]);
-    {
-      int t = 0;
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        const bf8 zh = swap_neg(hi[I]);
-#pragma unroll
-        for (int J = I; J < NB; ++J, ++t) {
-          accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], hi[J], accR[t], 0, 0, 0);
-          accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, hi[J], accI[t], 0, 0, 0);
-        }
-      }
+    for (int I = 0; I < NB; ++I) {
+      const u4 h = v[0][I], l = v[1][I];
+      yh[I] = __builtin_bit_cast(bf8, h);
+      yl[I] = __builtin_bit_cast(bf8, l);
+      const u2 rh2{lo_halves(h[0], h[1]), lo_halves(h[2], h[3])};
+      const u2 rl2{lo_halves(l[0], l[1]), lo_halves(l[2], l[3])};
+      reh[I] = __builtin_bit_cast(s4, rh2);
+      rel[I] = __builtin_bit_cast(s4, rl2);
+      imh[I] = __builtin_bit_cast(s4, u2{hi_halves(h[0], h[1]), hi_halves(h[2], h[3])});
+      iml[I] = __builtin_bit_cast(s4, u2{hi_halves(l[0], l[1]), hi_halves(l[2], l[3])});
+      nreh[I] = __builtin_bit_cast(s4, u2{rh2[0] ^ 0x80008000u, rh2[1] ^ 0x80008000u});
+      nrel[I] = __builtin_bit_cast(s4, u2{rl2[0] ^ 0x80008000u, rl2[1] ^ 0x80008000u});
     }
-    {
-      int t = 0;
+    int t = 0;
 #pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        const bf8 zh = swap_neg(hi[I]);
+    for (int I = 0; I < NB; ++I)
 #pragma unroll
-        for (int J = I; J < NB; ++J, ++t) {
-          accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hi[I], lo[J], accR[t], 0, 0, 0);
-          accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, lo[J], accI[t], 0, 0, 0);
-        }
+      for (int J = I; J < NB; ++J, ++t) {
+        accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[I], yh[J], accR[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(imh[I], reh[J], accI[t], 0, 0, 0);
+        accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yh[I], yl[J], accR[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nreh[I], imh[J], accI[t], 0, 0, 0);
+        accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(yl[I], yh[J], accR[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(imh[I], rel[J], accI[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(iml[I], reh[J], accI[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nreh[I], iml[J], accI[t], 0, 0, 0);
+        accI[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nrel[I], imh[J], accI[t], 0, 0, 0);
       }
-    }
-    {
-      int t = 0;
-#pragma unroll
-      for (int I = 0; I < NB; ++I) {
-        const bf8 zl = swap_neg(lo[I]);
-#pragma unroll
-        for (int J = I; J < NB; ++J, ++t) {
-          accR[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo[I], hi[J], accR[t], 0, 0, 0);
-          accI[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, hi[J], accI[t], 0, 0, 0);
-        }
-      }
-    }
   };
 #pragma unroll
   for (int s0 = 0; s0 < PF - 1; ++s0) {
@@ -647,8 +688,8 @@ struct Lds {
   static constexpr size_t oS = oVt + (kTailInS ? 0 : sizeof(EC) * RBM * Q * G);   // float2[PQ*PQ]
   static constexpr size_t oA = oS + sizeof(float2) * PQ * PQ;             // float2[P*P]
   static constexpr size_t oQidx = oA + sizeof(float2) * P * P;            // int64[G]
-  static constexpr size_t oOff = oQidx + sizeof(int64_t) * G;             // int[kMaxN]
-  static constexpr size_t oQflag = oOff + sizeof(int) * kMaxN;            // int[G]
+  static constexpr size_t oOff = oQidx + sizeof(int64_t) * G;             // uint32[kMaxN + kOffPad]
+  static constexpr size_t oQflag = oOff + sizeof(uint32_t) * (kMaxN + kOffPad);   // int[G]
   static constexpr size_t oQit = oQflag + sizeof(int) * G;                // int[G]
   static constexpr size_t oQeta = oQit + sizeof(int) * G;                 // float[G]
   static constexpr size_t bytes = ((oQeta + sizeof(float) * G) + 15) / 16 * 16;
@@ -672,7 +713,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   static_assert(PQ * PQ >= QQ, "LDS reuse");
 
   float2* const sS = reinterpret_cast<float2*>(lds + L::oS);     // S; then raw B; then tail scratch
-  int* const sOff = reinterpret_cast<int*>(lds + L::oOff);
+  uint32_t* const sOffB = reinterpret_cast<uint32_t*>(lds + L::oOff);
   float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
   EC* const sUA = reinterpret_cast<EC*>(lds + L::oUA);
   EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
@@ -689,20 +730,25 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   const int H = prm.H, W = prm.W;
   const int r_a = prm.r_a, r_b = prm.r_b;
 
+  // byte offset of each stencil entry from the window origin (kOut past n);
+  // samples are complex64 (8 bytes) or, on the mixed path, BF16 pairs (4)
+  constexpr int kSample = PREC ? 4 : 8;
   wave_sync();
-  for (int m = lane; m < n; m += 64) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
+  for (int m = lane; m < kMaxN + kOffPad; m += 64)
+    sOffB[m] = (m < n) ? uint32_t(((int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q - prm.st_min) * kSample)
+                       : kOut;
   wave_sync();
 
   // Operand rows of this lane: row rho = 16*I + (lane & 15) of the stacked
-  // snapshot, channel rho / q, sample rho % q.
-  int chan_off[NB];
-  bool row_ok[NB];
+  // snapshot, channel rho / q, sample rho % q; its byte offset inside block
+  // I's record, which starts in channel 16*I / q.
+  const int64_t plane = int64_t(H) * W * Q;
+  uint32_t loff[NB];
 #pragma unroll
   for (int I = 0; I < NB; ++I) {
     const int rho = 16 * I + (lane & 15);
-    row_ok[I] = rho < PQ;
     const int ch = rho / Q, j = rho - ch * Q;
-    chan_off[I] = row_ok[I] ? ch * H * W * Q + j : 0;
+    loff[I] = (rho < PQ) ? uint32_t(((ch - (16 * I) / Q) * plane + j) * kSample) : kOut;
   }
 
   // queue of pixels waiting for the batched tail: lane (g, k) holds row k of
@@ -856,13 +902,14 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       }
       continue;
     }
-    const float2* xp = prm.x + (int64_t(r) * W + c) * Q;
+    // window origin as a sample index (x and the split planes share the layout)
+    const int64_t win = (int64_t(r) * W + c) * Q + prm.st_min;
 
     // ---------------------------------------------------------------- a2 SCM
     if constexpr (PREC == 0)
-      scm_fp32<P, Q>(xp, sOff, chan_off, row_ok, n, sS);
+      scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS);
     else
-      scm_bf16x3<P, Q>(xp, sOff, chan_off, row_ok, n, sS);
+      scm_bf16x3<P, Q>(prm.xs + win, prm.xs + P * plane + win, plane, prm.rec_bytes / 2, sOffB, loff, n, sS);
 
     // ------------------------------------------------ a4 init, ||R||_F = ||S||_F
     float2 A[P * P];
@@ -1791,11 +1838,7 @@ __global__ __launch_bounds__(256, 1) void kstap_wide_kernel(const KParams prm) {
   run_pixels_wide<P, Q, RBM, MODE, PREC>(prm, first, count, lds);
 }
 
-__global__ void reset_counters(unsigned long long* c, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0ull;
-}
-
-// ---------------------------------------------------------------- dispatch
+// ---------------------------------------------------------------- launchers
 template <int P, int Q, int RBM, int PREC>
 int launch_one(int mode, const KParams& prm, hipStream_t stream) {
   int64_t units = (mode == kModeRun) ? int64_t(prm.nlogical) : (int64_t(prm.npix) + prm.pix_per_block - 1) / prm.pix_per_block;
@@ -1831,69 +1874,5 @@ int launch_persist(const KParams* descs, const int32_t* order, const int64_t* pr
   return hipGetLastError();
 }
 
-struct Entry {
-  int p, q, rbm, prec;
-  int (*fn)(int, const KParams&, hipStream_t);
-  int (*persist)(const KParams*, const int32_t*, const int64_t*, int, int, unsigned long long*, int, hipStream_t);
-  const void* persist_fn;
-};
-
-#define KSTAP_ENTRY(P, Q, R, X) \
-  {P, Q, R, X, &launch_one<P, Q, R, X>, &launch_persist<P, Q, R, X>, \
-   reinterpret_cast<const void*>(&kstap_persistent<P, Q, R, X>)}
-const Entry kTable[] = {
-    KSTAP_ENTRY(2, 8, 4, 0),  KSTAP_ENTRY(2, 16, 4, 0), KSTAP_ENTRY(2, 32, 4, 0),
-    KSTAP_ENTRY(3, 8, 4, 0),  KSTAP_ENTRY(3, 8, 8, 0),  KSTAP_ENTRY(3, 12, 4, 0), KSTAP_ENTRY(3, 12, 8, 0),
-    KSTAP_ENTRY(3, 16, 4, 0), KSTAP_ENTRY(3, 16, 8, 0), KSTAP_ENTRY(4, 8, 4, 0),  KSTAP_ENTRY(4, 16, 4, 0),
-    KSTAP_ENTRY(6, 8, 4, 0),
-    KSTAP_ENTRY(3, 8, 4, 1),  KSTAP_ENTRY(3, 8, 8, 1),  KSTAP_ENTRY(3, 12, 4, 1), KSTAP_ENTRY(3, 12, 8, 1),
-    KSTAP_ENTRY(3, 16, 4, 1), KSTAP_ENTRY(3, 16, 8, 1),
-    // wide pixels: one 4-wave workgroup per pixel (no persistent form)
-    {5, 24, 4, 0, &launch_wide<5, 24, 4, 0>, nullptr, nullptr},
-    {5, 24, 4, 1, &launch_wide<5, 24, 4, 1>, nullptr, nullptr},
-    {6, 16, 4, 0, &launch_wide<6, 16, 4, 0>, nullptr, nullptr},
-    {6, 16, 4, 1, &launch_wide<6, 16, 4, 1>, nullptr, nullptr},
-};
-#undef KSTAP_ENTRY
-
-const Entry* find(int p, int q, int r_b, int prec) {
-  const int rbm = (r_b <= 4) ? 4 : 8;
-  for (const Entry& e : kTable)
-    if (e.p == p && e.q == q && e.rbm == rbm && e.prec == prec) return &e;
-  return nullptr;
-}
-
 }  // namespace
-
-bool kernel_available(int p, int q, int r_b, int precision) { return find(p, q, r_b, precision) != nullptr; }
-
-int launch_pixels(int p, int q, int precision, int mode, const KParams& prm, hipStream_t stream) {
-  const Entry* e = find(p, q, prm.r_b, precision);
-  if (!e) return hipErrorInvalidValue;
-  return e->fn(mode, prm, stream);
-}
-
-int kernel_class(int p, int q, int r_b, int precision) {
-  const Entry* e = find(p, q, r_b, precision);
-  return (e && e->persist) ? int(e - kTable) : -1;
-}
-
-int launch_persistent(int cls, const KParams* descs, const int32_t* order, const int64_t* prefix, int nt, int ppb,
-                      unsigned long long* counter, int grid, hipStream_t stream) {
-  if (cls < 0 || cls >= int(sizeof(kTable) / sizeof(kTable[0])) || !kTable[cls].persist) return hipErrorInvalidValue;
-  return kTable[cls].persist(descs, order, prefix, nt, ppb, counter, grid, stream);
-}
-
-const void* persistent_kernel(int cls) {
-  if (cls < 0 || cls >= int(sizeof(kTable) / sizeof(kTable[0]))) return nullptr;
-  return kTable[cls].persist_fn;
-}
-
-const void* reset_kernel() { return reinterpret_cast<const void*>(&reset_counters); }
-
-int launch_reset(unsigned long long* counters, int n, hipStream_t stream) {
-  hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, stream, counters, n);
-  return hipGetLastError();
-}
-
 }  // namespace kstap

@@ -98,6 +98,29 @@ void valid_region(const stap_plan_s* pl, int H, int W, int* r0, int* r1, int* c0
   *c1 = std::max(*c0, W - std::max(0, pl->dc_max));
 }
 
+// The narrow kernels (p*q <= 64) read training vectors through buffer
+// records of 16 operand rows; a record starts at the window origin in the
+// channel of its first row and also reaches the next channel when the 16
+// rows straddle one.  Returns the record size in bytes and the smallest
+// stencil offset (dr*W + dc)*q in samples.
+static int64_t record_bytes(const stap_plan_s* pl, int H, int W, int64_t* st_min_out) {
+  const stap_config& c = pl->cfg;
+  int64_t st_min = 0, st_max = 0;
+  for (int m = 0; m < c.n; ++m) {
+    const int64_t o = (int64_t(pl->stencil[2 * m]) * W + pl->stencil[2 * m + 1]) * c.q;
+    st_min = (m == 0 || o < st_min) ? o : st_min;
+    st_max = (m == 0 || o > st_max) ? o : st_max;
+  }
+  const int pq = c.p * c.q;
+  int span = 0;
+  for (int row0 = 0; row0 < pq; row0 += 16) {
+    const int last = (row0 + 15 < pq) ? row0 + 15 : pq - 1;
+    span = std::max(span, last / c.q - row0 / c.q);
+  }
+  if (st_min_out) *st_min_out = st_min;
+  return (int64_t(span) * H * W * c.q + (st_max - st_min) + c.q) * 8;
+}
+
 stap_status fill_params(const stap_plan_s* pl, const void* x, int H, int W, kstap::KParams* k) {
   const stap_config& c = pl->cfg;
   std::memset(k, 0, sizeof(*k));
@@ -128,6 +151,10 @@ stap_status fill_params(const stap_plan_s* pl, const void* x, int H, int W, ksta
     k->st[2 * m + 1] = int16_t(pl->stencil[2 * m + 1]);
   }
   valid_region(pl, H, W, &k->r0, &k->r1, &k->c0, &k->c1);
+  int64_t st_min = 0;
+  const int64_t rec = record_bytes(pl, H, W, &st_min);
+  k->st_min = int32_t(st_min);
+  k->rec_bytes = uint32_t(std::min<int64_t>(rec, (int64_t(1) << 31) - 1));   // check_frame enforces < 2^31
   return STAP_OK;
 }
 
@@ -138,6 +165,10 @@ stap_status check_frame(const stap_plan_s* pl, const void* x, int H, int W) {
   const int64_t elems = int64_t(pl->cfg.p) * H * W * pl->cfg.q;
   if (elems >= (int64_t(1) << 31))
     return fail(STAP_ERR_INVALID_ARG, "frame of %lld complex samples exceeds 2^31 - 1", (long long)elems);
+  const int64_t rec = record_bytes(pl, H, W, nullptr);
+  if (pl->cfg.p * pl->cfg.q <= 64 && rec >= (int64_t(1) << 31))
+    return fail(STAP_ERR_UNSUPPORTED, "a %d x %d channel plane at q = %d is too large: a training-vector record spans %lld bytes (limit 2^31)",
+                H, W, pl->cfg.q, (long long)rec);
   return STAP_OK;
 }
 

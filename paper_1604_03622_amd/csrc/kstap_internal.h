@@ -17,6 +17,7 @@ constexpr int kMaxRB = 8;
 // (about 1.6 KB; the kernarg segment allows 4 KB).
 struct KParams {
   const float2* x;        // frame, complex64 [p][H][W][q]
+  const uint32_t* xs;     // mixed path: BF16 split of x, hi plane then lo plane, one packed pair per sample
   float* T;               // run: [H][W];  probe: [npix]
   uint8_t* D;             // run: [H][W] or null
   int32_t H, W;
@@ -28,6 +29,8 @@ struct KParams {
   float bs_norm2;         // ||b_s||^2
   float h_norm2;          // ||h||^2
   int32_t r0, r1, c0, c1; // valid region, half-open
+  int32_t st_min;         // smallest stencil offset (dr*W + dc)*q, in complex samples
+  uint32_t rec_bytes;     // bytes a training-vector buffer record spans from the window origin
   int32_t pix_per_block;  // run: consecutive tiled-order positions per workgroup
   int32_t nlogical;       // run: workgroups that carry pixels (grid is rounded up to 8)
   int64_t range_first;    // persistent: tiled-order position range [range_first, range_end)
@@ -78,8 +81,23 @@ __host__ __device__ inline bool tiled_pixel(int64_t pos, int H, int W, int* r, i
   return *r < H && *c < W;
 }
 
+// One built kernel: (p, q, r_b bound, precision) and its launchers.  The
+// tables live in the translation units that instantiate the kernels.
+struct Entry {
+  int p, q, rbm, prec;
+  bool planes;   // reads the split planes of the mixed path (narrow kernels, PREC 1)
+  int (*fn)(int mode, const KParams& prm, hipStream_t stream);
+  int (*persist)(const KParams* descs, const int32_t* order, const int64_t* prefix, int nt, int ppb,
+                 unsigned long long* counter, int grid, hipStream_t stream);   // null: no persistent form
+  const void* persist_fn;
+};
+
 // Returns true if a kernel is built for (p, q, r_b bound, precision).
 bool kernel_available(int p, int q, int r_b, int precision);
+
+// True if that kernel reads the split planes (KParams::xs) of the mixed path:
+// 2 * 4 bytes per complex sample of the frame, filled by launch_split.
+bool kernel_needs_planes(int p, int q, int r_b, int precision);
 
 // Enqueues the fused per-pixel kernel.  Returns a hipError_t value.
 int launch_pixels(int p, int q, int precision, int mode, const KParams& prm, hipStream_t stream);
@@ -92,6 +110,17 @@ int kernel_class(int p, int q, int r_b, int precision);
 // by prefix[] (device arrays); counter: device work counter (must be 0).
 int launch_persistent(int cls, const KParams* descs, const int32_t* order, const int64_t* prefix, int nt, int ppb,
                       unsigned long long* counter, int grid, hipStream_t stream);
+
+// Mixed path: for the n complex samples of x writes the packed BF16 pairs
+// xs[i] = hi = bf16(x[i]) and xs[n + i] = lo = bf16(x[i] - hi).  Returns a
+// hipError_t value.  split_kernel(): its handle (arguments: x, xs, n) for
+// explicit graph nodes, launched with split_grid(n) blocks of 256 threads.
+int launch_split(const float2* x, uint32_t* xs, int64_t n, hipStream_t stream);
+const void* split_kernel();
+inline unsigned split_grid(int64_t n) {
+  const int64_t b = (n + 255) / 256;
+  return unsigned(b < 256 * 32 ? (b > 0 ? b : 1) : 256 * 32);
+}
 
 // Zeroes n device counters with a kernel (no memset node in graphs).
 int launch_reset(unsigned long long* counters, int n, hipStream_t stream);

@@ -1,0 +1,21 @@
+// Instantiations of the narrow mixed-path kernels (split-BF16 covariance, FP64 solves).
+#include "kstap_device.h"
+
+namespace kstap {
+
+#define KSTAP_ENTRY(P, Q, R, X) \
+  {P, Q, R, X, X == 1, &launch_one<P, Q, R, X>, &launch_persist<P, Q, R, X>, \
+   reinterpret_cast<const void*>(&kstap_persistent<P, Q, R, X>)}
+// the table is a local static of a host function (a namespace-scope const
+// array would also be emitted, unresolvable, for the device)
+const Entry* entries_bf16(int* count) {
+  static const Entry t[] = {
+      KSTAP_ENTRY(3, 8, 4, 1),  KSTAP_ENTRY(3, 8, 8, 1),  KSTAP_ENTRY(3, 12, 4, 1), KSTAP_ENTRY(3, 12, 8, 1),
+      KSTAP_ENTRY(3, 16, 4, 1), KSTAP_ENTRY(3, 16, 8, 1),
+  };
+  *count = int(sizeof(t) / sizeof(t[0]));
+  return t;
+}
+#undef KSTAP_ENTRY
+
+}  // namespace kstap

@@ -85,6 +85,8 @@ struct Frame {
   uint8_t* D_out = nullptr;
   int cls = -1;
   size_t off = 0, bytes = 0, x_bytes = 0;
+  bool planes = false;     // mixed path: split planes at off + planes_off
+  size_t planes_off = 0;
   int64_t cursor = 0, total = 0, inflight_end = 0;   // cursor/inflight_end/npos: tiled-order positions
   int64_t npos = 0;
   double t_submit = 0, t_done = 0;
@@ -93,10 +95,15 @@ struct Frame {
   hipEvent_t ev_up = nullptr, ev_down = nullptr;
 };
 
-size_t frame_bytes(const stap_plan_s* pl, int H, int W, bool x_on_device, size_t* x_bytes) {
+// Device bytes of one frame: [x, unless it is already on the device] [T] [D]
+// [split planes of the mixed path, if its kernel reads them].
+size_t frame_bytes(const stap_plan_s* pl, int H, int W, bool x_on_device, size_t* x_bytes, size_t* planes_off) {
+  const stap_config& c = pl->cfg;
   const size_t px = size_t(H) * W;
-  *x_bytes = x_on_device ? 0 : px * pl->cfg.p * pl->cfg.q * 8;
-  return (*x_bytes + 255) / 256 * 256 + (px * 4 + 255) / 256 * 256 + (px + 255) / 256 * 256;
+  *x_bytes = x_on_device ? 0 : px * c.p * c.q * 8;
+  *planes_off = (*x_bytes + 255) / 256 * 256 + (px * 4 + 255) / 256 * 256 + (px + 255) / 256 * 256;
+  const size_t planes = kstap::kernel_needs_planes(c.p, c.q, c.r_b, c.precision) ? px * c.p * c.q * 8 : 0;
+  return *planes_off + (planes + 255) / 256 * 256;
 }
 
 }  // namespace
@@ -168,6 +175,13 @@ void stap_server_s::admit_locked() {
     hipError_t e = hipSuccess;
     if (!f->x_on_device)
       e = hipMemcpyAsync(arena_base + off, f->x_src, f->x_bytes, hipMemcpyHostToDevice, s_copy);
+    if (e == hipSuccess && f->planes) {   // the mixed path's split, behind the upload
+      const void* x = f->x_on_device ? f->x_src : static_cast<const void*>(arena_base + off);
+      const stap_config& c = f->plan->cfg;
+      e = hipError_t(kstap::launch_split(static_cast<const float2*>(x),
+                                         reinterpret_cast<uint32_t*>(arena_base + off + f->planes_off),
+                                         int64_t(c.p) * f->H * f->W * c.q, s_copy));
+    }
     if (e == hipSuccess) e = hipEventRecord(f->ev_up, s_copy);
     if (e != hipSuccess) {
       finish(f, STAP_ERR_DEVICE, hipGetErrorString(e));
@@ -225,6 +239,7 @@ void stap_server_s::loop() {
       fill_params(f->plan, x, f->H, f->W, &k);
       const size_t xb = (f->x_bytes + 255) / 256 * 256;
       const size_t px = size_t(f->H) * f->W;
+      if (f->planes) k.xs = reinterpret_cast<const uint32_t*>(arena_base + f->off + f->planes_off);
       k.T = reinterpret_cast<float*>(arena_base + f->off + xb);
       k.D = reinterpret_cast<uint8_t*>(arena_base + f->off + xb + (px * 4 + 255) / 256 * 256);
       k.range_first = f->cursor;
@@ -383,7 +398,8 @@ stap_status stap_server_submit(stap_server_t* srv, const stap_plan_t* plan, cons
   f->T_out = T_host;
   f->D_out = D_host;
   f->cls = cls;
-  f->bytes = frame_bytes(plan, H, W, f->x_on_device, &f->x_bytes);
+  f->bytes = frame_bytes(plan, H, W, f->x_on_device, &f->x_bytes, &f->planes_off);
+  f->planes = kstap::kernel_needs_planes(plan->cfg.p, plan->cfg.q, plan->cfg.r_b, plan->cfg.precision);
   f->total = int64_t(H) * W;
   f->npos = kstap::tiled_positions(H, W);
   if (f->bytes > srv->budget) {
