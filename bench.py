@@ -32,6 +32,33 @@ WORKLOADS = {
 }
 
 
+# rocprofv3 summary of the dominant kernel on the full frame: its HBM bytes
+# per launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size) stand
+# only while the kernel sources hash to the value recorded beside them.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "kstap_kernel_p3q16_full_frame_fp32.md")
+
+
+def profiled_traffic(workload):
+    if workload != "full_frame" or not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    import hashlib
+    fields = {}
+    for line in open(TRAFFIC_PROFILE):
+        k, sep, v = line.partition(":")
+        if sep and k in ("traffic_bytes_per_launch", "kernel_sources", "kernel_sources_sha256"):
+            fields[k] = v.strip()
+    if len(fields) != 3:
+        return None
+    h = hashlib.sha256()
+    for f in fields["kernel_sources"].split():
+        path = os.path.join(ROOT, f)
+        if not os.path.exists(path):
+            return None
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return int(fields["traffic_bytes_per_launch"]) if h.hexdigest() == fields["kernel_sources_sha256"] else None
+
+
 def scm_flops_per_pixel(p, q, n):
     """Hermitian sample covariance: 4 n pq (pq + 1) real flops per pixel."""
     pq = p * q
@@ -348,7 +375,7 @@ def main():
             "peak": MFMA_FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / MFMA_FP32_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": profiled_traffic(args.workload),   # HBM bytes per launch, rocprofv3 counters
         },
         "cpu_baseline": cpu,
     }

@@ -1,5 +1,5 @@
 // Internal interface between the host runtime (kstap_api.cpp) and the HIP
-// kernels (kstap_kernels.hip).  Not part of the public ABI.
+// kernels (kstap_device.h and the kstap_kern_*.hip instantiations).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
