@@ -284,25 +284,26 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
   return step;
 }
 
-// Dominant eigenvector of a Hermitian P x P matrix held identically by every
-// lane (power iteration; stop on ||M u - (u^H M u) u|| <= tol ||M u||).
-template <int P, typename C>
-__device__ __forceinline__ void power_top(const C (&M)[P * P], C (&u)[P], bool cold, int max_steps, double tol) {
+// Dominant eigenvector of a Hermitian P x P matrix, the same for every lane;
+// M(i, j) returns its entries (registers or LDS).  Power iteration; stop on
+// ||M u - (u^H M u) u|| <= tol ||M u||.
+template <int P, typename C, typename MF>
+__device__ __forceinline__ void power_top(MF M, C (&u)[P], bool cold, int max_steps, double tol) {
   using S = decltype(C{}.x);
   if (cold) {
     int jb = 0;
-    S db = M[0].x;
+    S db = M(0, 0).x;
 #pragma unroll
     for (int j = 1; j < P; ++j)
-      if (M[j * P + j].x > db) {
-        db = M[j * P + j].x;
+      if (M(j, j).x > db) {
+        db = M(j, j).x;
         jb = j;
       }
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       C s = czero<C>();
 #pragma unroll
-      for (int j = 0; j < P; ++j) s = (j == jb) ? M[i * P + j] : s;
+      for (int j = 0; j < P; ++j) s = (j == jb) ? M(i, j) : s;
       u[i] = s;
     }
     S nn = 0;
@@ -319,7 +320,7 @@ __device__ __forceinline__ void power_top(const C (&M)[P * P], C (&u)[P], bool c
     for (int i = 0; i < P; ++i) {
       C s = czero<C>();
 #pragma unroll
-      for (int j = 0; j < P; ++j) s = cfma(M[i * P + j], u[j], s);
+      for (int j = 0; j < P; ++j) s = cfma(M(i, j), u[j], s);
       w[i] = s;
       lam += u[i].x * s.x + u[i].y * s.y;
       wn += cabs2(s);
@@ -760,7 +761,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   int nq = 0;
 
   // ------------------------------------------------ a6 + a8 for G pixels
-  auto tail = [&](int nfill) {
+  auto tail = [&](int nfill) __attribute__((always_inline)) {
     const bool slot_ok = tg < nfill;
     const bool rok = slot_ok && tk < Q;
     const int flag = slot_ok ? sQflag[tg] : 1;
@@ -966,7 +967,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 
       // one sweep over S: residual of (A, bv) if RES, then the new b and the
       // partial sums of R conj(b)
-      auto sweep = [&](bool res) {
+      auto sweep = [&](bool res) __attribute__((always_inline)) {
         const float ainv = 1.f / anorm2;
         float2 ap[P * P];
 #pragma unroll
@@ -1015,7 +1016,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       for (int i = 0; i < P; ++i) ua[i] = czero<EC>();
 #pragma unroll
       for (int c = 0; c < RAM; ++c) va[c] = czero<EC>();
-      auto eig_a = [&](bool cold) {
+      auto eig_a = [&](bool cold) __attribute__((always_inline)) {
         EC Ah[P * P];
 #pragma unroll
         for (int i = 0; i < P; ++i)
@@ -1023,7 +1024,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
           for (int j = 0; j < P; ++j)
             Ah[i * P + j] = cscale(cadd(cto<EC>(Ap[i * P + j]), cconj(cto<EC>(Ap[j * P + i]))), ES(0.5));
         if (r_a == 1) {
-          power_top<P, EC>(Ah, ua, cold, 500, PREC ? 1e-12 : 2e-6);
+          power_top<P, EC>([&](int i, int j) { return Ah[i * P + j]; }, ua, cold, 500, PREC ? 1e-12 : 2e-6);
           ES lam = 0;
 #pragma unroll
           for (int i = 0; i < P; ++i) {
@@ -1238,7 +1239,9 @@ struct WideLds {
   static constexpr size_t oAh = oUA + sizeof(EC) * P * RAM;          // EC[P*P]
   static constexpr size_t oVa = oAh + sizeof(EC) * P * P;            // EC[P*RAM]
   static constexpr size_t oA = oVa + sizeof(EC) * P * RAM;           // float2[P*P]
-  static constexpr size_t oOff = oA + sizeof(float2) * P * P;        // int[kMaxN]
+  static constexpr size_t oAp = oA + sizeof(float2) * P * P;         // float2[P*P]: block sums (A_0, R b*)
+  static constexpr size_t oB = oAp + sizeof(float2) * P * P;         // float2[Q*Q]: current b
+  static constexpr size_t oOff = oB + sizeof(float2) * Q * Q;        // int[kMaxN]
   static constexpr size_t bytes = (oOff + sizeof(int) * kMaxN + 15) / 16 * 16;
 };
 
@@ -1293,9 +1296,21 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
   EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
   EC* const sVa = reinterpret_cast<EC*>(lds + L::oVa);
   float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
+  float2* const sAp = reinterpret_cast<float2*>(lds + L::oAp);
+  float2* const sB = reinterpret_cast<float2*>(lds + L::oB);
   int* const sOff = reinterpret_cast<int*>(lds + L::oOff);
 
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  // entries of a q x q block a lane visits in the block passes: e = lane + 64 m,
+  // at row-major (k*QS + l) and transposed (l*QS + k) offsets
+  constexpr int NL = (QQ + 63) / 64;
+  int eo[NL], et[NL];
+#pragma unroll
+  for (int m = 0; m < NL; ++m) {
+    const int e = lane + 64 * m, k = e / Q, l = e - (e / Q) * Q;
+    eo[m] = k * QS + l;
+    et[m] = l * QS + k;
+  }
   const int n = prm.n, H = prm.H, W = prm.W;
   const int r_a = prm.r_a, r_b = prm.r_b;
 
@@ -1373,7 +1388,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     for (int u = 0; u < MYP; ++u) accR[u] = accI[u] = f4{0.f, 0.f, 0.f, 0.f};
     const int nch = (n + 15) >> 4;
     float2 pre[NIT];
-    auto gload = [&](int ch) {
+    auto gload = [&](int ch) __attribute__((always_inline)) {
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
         const int m = ch * 16 + it_v[it];
@@ -1381,7 +1396,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         pre[it] = load_or_zero(xp + it_off[it] + sOff[ok ? m : 0], ok);
       }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf) __attribute__((always_inline)) {
       char* base = stage + buf * L::stage1;
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
@@ -1412,7 +1427,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       const int g = lane >> 4, rr = lane & 15;
       if constexpr (PREC == 1) {
         // operand of block I: row 16 I + rr, vectors 4g..4g+3 (re, im) = 16 bytes
-        auto ld = [&](int I, bool lo) -> bf8 {
+        auto ld = [&](int I, bool lo) __attribute__((always_inline)) -> bf8 {
           const int row = 16 * I + rr;
           if (row >= PQ) return __builtin_bit_cast(bf8, u4{0u, 0u, 0u, 0u});
           const char* p = base + size_t((lo ? NB * 16 : 0) + row) * L::rowb + g * 16;
@@ -1434,7 +1449,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         // 4 K-steps of 4 vectors: lane (row rr, vector 4 s + g)
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
-          auto ld = [&](int I) -> float2 {
+          auto ld = [&](int I) __attribute__((always_inline)) -> float2 {
             const int row = 16 * I + rr;
             if (row >= PQ) return cz();
             return reinterpret_cast<const float2*>(base + size_t(row) * L::rowb)[4 * s4 + g];
@@ -1474,66 +1489,71 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     block_sync();
 
     // S(i,j)[k][l] for any (i, j)
-    auto Sget = [&](int i, int j, int k, int l) -> float2 {
+    auto Sget = [&](int i, int j, int k, int l) __attribute__((always_inline)) -> float2 {
       if (i <= j) return sS[((i * P - i * (i - 1) / 2 + (j - i)) * Q + k) * QS + l];
       return cconj(sS[((j * P - j * (j - 1) / 2 + (i - j)) * Q + l) * QS + k]);
+    };
+
+    // Block pass: out[ij] = scale * sum_kl conj(w_kl) S(i,j)_kl for the P*P
+    // blocks, dealt round-robin to the 4 waves; a wave's lanes split the q x q
+    // entries (this lane: e = lane + 64 m, weight wv[m]) and reduce with DPP.
+    // Optionally accumulates sum |S(i,j)_kl|^2 of the visited entries in *nr.
+    // out[] is complete after the next block_sync.
+    auto block_pass = [&](const float2 (&wv)[NL], float scale, float2* out, float* nr) {
+      for (int u = 0; u < (P * P + 3) / 4; ++u) {
+        const int ij = wave + 4 * u;
+        if (ij >= P * P) break;   // uniform per wave
+        const int i = ij / P, j = ij - (ij / P) * P;
+        const bool up = i <= j;
+        const int a = up ? i : j, b = up ? j : i;
+        const int base = (a * P - a * (a - 1) / 2 + (b - a)) * Q * QS;
+        float2 acc = cz();
+        float n2 = 0.f;
+#pragma unroll
+        for (int m = 0; m < NL; ++m) {
+          if (lane + 64 * m < QQ) {
+            float2 sv = sS[base + (up ? eo[m] : et[m])];
+            sv.y = up ? sv.y : -sv.y;
+            acc = ccfma(wv[m], sv, acc);
+            n2 += cabs2(sv);
+          }
+        }
+        if (nr) *nr += n2;
+        acc.x = wsum(acc.x);
+        acc.y = wsum(acc.y);
+        if (lane == 0) out[ij] = cscale(acc, scale);
+      }
     };
 
     // ------------------------------------------------ a4 init, ||R||_F = ||S||_F
     float2 A[P * P];
     double normR2;
     {
-      float acc[2 * P * P + 2];
+      float2 wv[NL];
 #pragma unroll
-      for (int e = 0; e < 2 * P * P + 2; ++e) acc[e] = 0.f;
+      for (int m = 0; m < NL; ++m) wv[m] = make_float2(1.f, 0.f);
       float nr = 0.f;
-#pragma unroll
-      for (int t = 0; t < NE; ++t) {
-        const int e = tid + 256 * t;
-        if (e < QQ) {
-          const int k = e / Q, l = e - (e / Q) * Q;
-#pragma unroll
-          for (int i = 0; i < P; ++i)
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-              const float2 s = Sget(i, j, k, l);
-              acc[2 * (i * P + j)] += s.x;
-              acc[2 * (i * P + j) + 1] += s.y;
-              nr += cabs2(s);
-            }
-        }
-      }
-      normR2 = block_sumd(double(nr), redd);
-      block_sum<2 * P * P + 2>(acc, red);
+      block_pass(wv, 1.f / float(QQ), sAp, &nr);
+      normR2 = block_sumd(double(nr), redd);   // its barriers also publish sAp
       float an = 0.f;
 #pragma unroll
       for (int e = 0; e < P * P; ++e) {
-        A[e] = make_float2(acc[2 * e] / float(QQ), acc[2 * e + 1] / float(QQ));
+        A[e] = sAp[e];
         an += cabs2(A[e]);
       }
       if (double(an) <= 1e-24 * normR2) {   // fallback: partial trace R vec(I_q)
-        float pt[2 * P * P + 2];
 #pragma unroll
-        for (int e = 0; e < 2 * P * P + 2; ++e) pt[e] = 0.f;
-#pragma unroll
-        for (int t = 0; t < NE; ++t) {
-          const int e = tid + 256 * t;
-          if (e < QQ && e / Q == e - (e / Q) * Q) {
-            const int k = e / Q;
-#pragma unroll
-            for (int i = 0; i < P; ++i)
-#pragma unroll
-              for (int j = 0; j < P; ++j) {
-                const float2 s = Sget(i, j, k, k);
-                pt[2 * (i * P + j)] += s.x;
-                pt[2 * (i * P + j) + 1] += s.y;
-              }
-          }
+        for (int m = 0; m < NL; ++m) {
+          const int e = lane + 64 * m;
+          wv[m] = (e < QQ && e / Q == e - (e / Q) * Q) ? make_float2(1.f, 0.f) : cz();
         }
-        block_sum<2 * P * P + 2>(pt, red);
+        block_sync();
+        block_pass(wv, 1.f, sAp, nullptr);
+        block_sync();
 #pragma unroll
-        for (int e = 0; e < P * P; ++e) A[e] = make_float2(pt[2 * e], pt[2 * e + 1]);
+        for (int e = 0; e < P * P; ++e) A[e] = sAp[e];
       }
+      block_sync();
     }
 
     float eta = 0.f;
@@ -1551,24 +1571,22 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     for (int cc = 0; cc < RAM; ++cc) va[cc] = czero<EC>();
 
     if (!zero && !bad) {
-      float2 Ap[P * P];
       double resid = 0.0;
       float anorm2 = 0.f;
 #pragma unroll
       for (int e = 0; e < P * P; ++e) anorm2 += cabs2(A[e]);
-      auto sweep = [&](bool res) {
+      // One LR-Kron half-step pair: the residual of (A, b) if RES, the new
+      // b = R^T conj(a) / ||a||^2 (lane-owned entries, all blocks), then the
+      // block pass R conj(b) / ||b||^2 into sAp.
+      auto sweep = [&](bool res) __attribute__((always_inline)) {
         const float ainv = 1.f / anorm2;
-        float acc[2 * P * P + 2];
-#pragma unroll
-        for (int e = 0; e < 2 * P * P + 2; ++e) acc[e] = 0.f;
         double rr = 0.0;
+        float bb = 0.f;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
           const int e = tid + 256 * t;
           if (e < QQ) {
             const int k = e / Q, l = e - (e / Q) * Q;
-            // first pass over the blocks: residual of the previous iterate and
-            // the new b; second pass (S re-read): partial sums of R conj(b)
             float a2 = 0.f;
             float2 bn = cz();
 #pragma unroll
@@ -1582,40 +1600,38 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
             if (res) rr += double(a2);
             bn = cscale(bn, ainv);
             bv[t] = bn;
-            acc[2 * P * P] += cabs2(bn);
-#pragma unroll
-            for (int i = 0; i < P; ++i)
-#pragma unroll
-              for (int j = 0; j < P; ++j) {
-                const float2 pa = ccfma(bn, Sget(i, j, k, l), cz());
-                acc[2 * (i * P + j)] += pa.x;
-                acc[2 * (i * P + j) + 1] += pa.y;
-              }
+            bb += cabs2(bn);
+            sB[e] = bn;
           } else {
             bv[t] = cz();
           }
         }
-        block_sum<2 * P * P + 2>(acc, red);
-        const float binv = 1.f / acc[2 * P * P];
-#pragma unroll
-        for (int ij = 0; ij < P * P; ++ij) Ap[ij] = make_float2(acc[2 * ij] * binv, acc[2 * ij + 1] * binv);
+        float bsum[1] = {bb};
+        block_sum<1>(bsum, red);   // its barriers also publish sB
         if (res) resid = block_sumd(rr, redd);
+        float2 wv[NL];
+#pragma unroll
+        for (int m = 0; m < NL; ++m) wv[m] = (lane + 64 * m < QQ) ? sB[lane + 64 * m] : cz();
+        block_pass(wv, 1.f / bsum[0], sAp, nullptr);
+        block_sync();
       };
-      auto eig_a = [&](bool cold) {
-        EC Ah[P * P];
-#pragma unroll
-        for (int i = 0; i < P; ++i)
-#pragma unroll
-          for (int j = 0; j < P; ++j)
-            Ah[i * P + j] = cscale(cadd(cto<EC>(Ap[i * P + j]), cconj(cto<EC>(Ap[j * P + i]))), ES(0.5));
+      // EIG_{r_a} of Herm(A'), A' = sAp
+      auto eig_a = [&](bool cold) __attribute__((always_inline)) {
+        if (tid < P * P) {
+          const int i = tid / P, j = tid - (tid / P) * P;
+          const EC h = cscale(cadd(cto<EC>(sAp[i * P + j]), cconj(cto<EC>(sAp[j * P + i]))), ES(0.5));
+          sAh[tid] = h;
+          sA[tid] = tof(h);
+        }
+        block_sync();
         if (r_a == 1) {
-          power_top<P, EC>(Ah, ua, cold, 500, PREC ? 1e-12 : 2e-6);
+          power_top<P, EC>([&](int i, int j) { return sAh[i * P + j]; }, ua, cold, 500, PREC ? 1e-12 : 2e-6);
           ES lam = 0;
 #pragma unroll
           for (int i = 0; i < P; ++i) {
             EC s = czero<EC>();
 #pragma unroll
-            for (int j = 0; j < P; ++j) s = cfma(Ah[i * P + j], ua[j], s);
+            for (int j = 0; j < P; ++j) s = cfma(sAh[i * P + j], ua[j], s);
             lam += ua[i].x * s.x + ua[i].y * s.y;
           }
           anorm2 = 0.f;
@@ -1626,17 +1642,9 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
               A[i * P + j] = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
               anorm2 += cabs2(A[i * P + j]);
             }
+          block_sync();   // sAh is rewritten by the next call
           return;
         }
-        block_sync();
-        if (tid == 0) {
-#pragma unroll
-          for (int e = 0; e < P * P; ++e) {
-            sA[e] = tof(Ah[e]);
-            sAh[e] = Ah[e];
-          }
-        }
-        block_sync();
         float2 mrow[P];
 #pragma unroll
         for (int j = 0; j < P; ++j) mrow[j] = sA[(lane < P ? lane : 0) * P + j];
@@ -1683,20 +1691,21 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
           }
         block_sync();
       };
-      sweep(false);
-      eig_a(true);
-      iters = 1;
+      // sweep 0 has no residual; after sweep k >= 1 the stop rule looks at
+      // eta_k (one call site per lambda keeps the code, and its registers, small)
       double eta_prev = INFINITY;
-      while (true) {
-        sweep(true);
-        const double e = sqrt(resid / normR2);
-        eta = float(e);
-        const bool stop = iters >= prm.max_iter ||
-                          (prm.eps > 0.0 && iters >= prm.min_iter && fabs(e - eta_prev) <= prm.eps);
-        if (stop) break;
-        eta_prev = e;
-        eig_a(false);
-        ++iters;
+      for (int k = 0;; ++k) {
+        sweep(k > 0);
+        if (k > 0) {
+          const double e = sqrt(resid / normR2);
+          eta = float(e);
+          const bool stop = iters >= prm.max_iter ||
+                            (prm.eps > 0.0 && iters >= prm.min_iter && fabs(e - eta_prev) <= prm.eps);
+          if (stop) break;
+          eta_prev = e;
+        }
+        eig_a(k == 0);
+        iters = k + 1;
       }
     }
     // U_A of this pixel (rows of the r_a = 1 power iterate, or the subspace)
