@@ -202,7 +202,8 @@ def form_serving(kstap, torch, nframes):
         xh = torch.empty(xd.shape, dtype=torch.complex64, pin_memory=True)
         xh.copy_(xd)
         del xd
-        frames.append((kstap.Plan(p=3, q=sp.q, n=n, r_a=1, r_b=3), xh, sp.H * sp.W))
+        frames.append((kstap.Plan(p=3, q=sp.q, n=n, r_a=1, r_b=3), xh, sp.H * sp.W,
+                       kstap.Plan(p=3, q=sp.q, n=n, r_a=1, r_b=3, precision="bf16x3")))
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     tot_px = sum(f[2] for f in frames)
@@ -211,7 +212,7 @@ def form_serving(kstap, torch, nframes):
     def plain(arrivals):
         lat = []
         t0 = time.perf_counter()
-        for (pl, xh, npx), ta in zip(frames, arrivals):
+        for (pl, xh, npx, _), ta in zip(frames, arrivals):
             now = time.perf_counter() - t0
             if ta > now:
                 time.sleep(ta - now)
@@ -223,17 +224,17 @@ def form_serving(kstap, torch, nframes):
         span = time.perf_counter() - t0
         return lat, span
 
-    def served(arrivals):
+    def served(arrivals, mixed=False):
         srv = kstap.Server(hbm_budget_bytes=24 << 30, max_inflight=16, step_pixels=1 << 20)
         tickets = []
         t0 = time.perf_counter()
 
         def submit():
-            for (pl, xh, npx), ta in zip(frames, arrivals):
+            for (pl, xh, npx, plm), ta in zip(frames, arrivals):
                 now = time.perf_counter() - t0
                 if ta > now:
                     time.sleep(ta - now)
-                tickets.append(srv.submit(pl, xh))
+                tickets.append(srv.submit(plm if mixed else pl, xh))
         th = threading.Thread(target=submit)
         th.start()
         th.join()
@@ -257,12 +258,17 @@ def form_serving(kstap, torch, nframes):
     for name, arrivals in (("burst", [0.0] * len(frames)), ("poisson", list(arr))):
         pl_lat, pl_span = plain(arrivals)
         sv_lat, sv_span, st = served(arrivals)
+        mx_lat, mx_span, mst = served(arrivals, mixed=True)
         out[name] = dict(
             plain=dict(pixels_per_s=tot_px / pl_span, p50_s=float(np.percentile(pl_lat, 50)),
                        p99_s=float(np.percentile(pl_lat, 99))),
             server=dict(pixels_per_s=tot_px / sv_span, p50_s=float(np.percentile(sv_lat, 50)),
-                        p99_s=float(np.percentile(sv_lat, 99)), server_stats=st))
+                        p99_s=float(np.percentile(sv_lat, 99)), server_stats=st),
+            server_bf16x3=dict(pixels_per_s=tot_px / mx_span, p50_s=float(np.percentile(mx_lat, 50)),
+                               p99_s=float(np.percentile(mx_lat, 99)), server_stats=mst),
+            mixed_served_over_plain_fp32=pl_span / mx_span)
         _log(f"serving {name}: server {tot_px / sv_span / 1e6:.1f} Mpx/s p99 {np.percentile(sv_lat, 99) * 1e3:.0f} ms; "
+             f"server bf16x3 {tot_px / mx_span / 1e6:.1f} Mpx/s p99 {np.percentile(mx_lat, 99) * 1e3:.0f} ms; "
              f"plain {tot_px / pl_span / 1e6:.1f} Mpx/s p99 {np.percentile(pl_lat, 99) * 1e3:.0f} ms")
     return out
 

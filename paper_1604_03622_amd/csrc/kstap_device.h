@@ -186,12 +186,13 @@ __device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
     if (c >= r) continue;
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
-      C h[RM];
+      // classical GS: every projection uses the column as it entered the
+      // pass (w0), applied as soon as it is known (one coefficient live)
+      const C w0 = w[c];
 #pragma unroll
-      for (int a = 0; a < c; ++a) h[a] = gsum<QP>(act ? ccfma(w[a], w[c], czero<C>()) : czero<C>());
-      if (act) {
-#pragma unroll
-        for (int a = 0; a < c; ++a) w[c] = csub(w[c], cmul(w[a], h[a]));
+      for (int a = 0; a < c; ++a) {
+        const C h = gsum<QP>(act ? ccfma(w[a], w0, czero<C>()) : czero<C>());
+        if (act) w[c] = csub(w[c], cmul(w[a], h));
       }
     }
     const S nn = gsum<QP>(act ? cabs2(w[c]) : S(0));
@@ -252,15 +253,14 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
 #pragma unroll
       for (int b = 0; b < RM; ++b) {
         if (b >= r) continue;
-        C hb[RM];
+        C rr = w[b];
 #pragma unroll
-        for (int a = 0; a < RM; ++a)
-          if (a < r) hb[a] = gsum<QP>(row_ok ? ccfma(v[a], w[b], czero<C>()) : czero<C>());
+        for (int a = 0; a < RM; ++a) {
+          if (a >= r) continue;
+          const C hb = gsum<QP>(row_ok ? ccfma(v[a], w[b], czero<C>()) : czero<C>());
+          rr = csub(rr, cmul(v[a], hb));
+        }
         if (row_ok) {
-          C rr = w[b];
-#pragma unroll
-          for (int a = 0; a < RM; ++a)
-            if (a < r) rr = csub(rr, cmul(v[a], hb[a]));
           rn += cabs2(rr);
           wn += cabs2(w[b]);
         }
@@ -280,6 +280,109 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
     tested = true;
     ++step;
     if (__ballot(!done) == 0 || step >= max_steps) break;
+  }
+  return step;
+}
+
+// Top-r invariant subspace of a small Hermitian P x P matrix (the factor A),
+// computed identically by every lane with no cross-lane traffic: the
+// subspace iteration, CGS2 and stopping rule of group_subspace, on a matrix
+// read through M(i, j).  V[c][i] is entry i of basis column c; `cold` starts
+// from M * Omega, otherwise V is the warm start.  Returns the step count.
+template <int RM, int P, typename C, typename MF>
+__device__ __forceinline__ int uniform_subspace(MF M, int r, C (&V)[RM][P], bool cold, int max_steps, double tol) {
+  using S = decltype(C{}.x);
+  if (cold) {
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) V[c][i] = (c < r) ? cto<C>(omega(i, c)) : czero<C>();
+  }
+  bool tested = !cold;
+  bool done = false;
+  int step = 0;
+  while (true) {
+    C Wm[RM][P];
+#pragma unroll
+    for (int c = 0; c < RM; ++c)
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        C sacc = czero<C>();
+        if (c < r) {
+#pragma unroll
+          for (int j = 0; j < P; ++j) sacc = cfma(M(i, j), V[c][j], sacc);
+        }
+        Wm[c][i] = sacc;
+      }
+    bool conv = false;
+    if (tested) {
+      // residual W - V (V^H W)
+      S rn = 0, wn = 0;
+#pragma unroll
+      for (int b = 0; b < RM; ++b) {
+        if (b >= r) continue;
+        C hb[RM];
+#pragma unroll
+        for (int a = 0; a < RM; ++a) {
+          C d = czero<C>();
+          if (a < r) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) d = ccfma(V[a][i], Wm[b][i], d);
+          }
+          hb[a] = d;
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          C rr = Wm[b][i];
+#pragma unroll
+          for (int a = 0; a < RM; ++a)
+            if (a < r) rr = csub(rr, cmul(V[a][i], hb[a]));
+          rn += cabs2(rr);
+          wn += cabs2(Wm[b][i]);
+        }
+      }
+      conv = rn <= S(tol * tol) * wn;
+    }
+    // CGS2 on the columns of W
+#pragma unroll
+    for (int c = 0; c < RM; ++c) {
+      if (c >= r) continue;
+#pragma unroll
+      for (int pass = 0; pass < 2; ++pass) {
+        C h[RM];
+#pragma unroll
+        for (int a = 0; a < RM; ++a) {
+          C d = czero<C>();
+          if (a < c) {
+#pragma unroll
+            for (int i = 0; i < P; ++i) d = ccfma(Wm[a][i], Wm[c][i], d);
+          }
+          h[a] = d;
+        }
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+#pragma unroll
+          for (int a = 0; a < RM; ++a)
+            if (a < c) Wm[c][i] = csub(Wm[c][i], cmul(Wm[a][i], h[a]));
+      }
+      S nn = 0;
+#pragma unroll
+      for (int i = 0; i < P; ++i) nn += cabs2(Wm[c][i]);
+      const S inv = S(1) / xsqrt(xmax(nn, tiny<S>()));
+#pragma unroll
+      for (int i = 0; i < P; ++i) Wm[c][i] = cscale(Wm[c][i], inv);
+    }
+    // as in group_subspace: keep the first basis computed from a converged one
+    if (!done) {
+#pragma unroll
+      for (int c = 0; c < RM; ++c)
+#pragma unroll
+        for (int i = 0; i < P; ++i) V[c][i] = Wm[c][i];
+    }
+    done = done || conv;
+    tested = true;
+    ++step;
+    if (done || step >= max_steps) break;
   }
   return step;
 }
@@ -1011,11 +1114,8 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 
       // EIG_{r_a}: A <- U (U^H A' U) U^H with U the top-r_a subspace of Herm(A')
       EC ua[P];
-      EC va[RAM];
 #pragma unroll
       for (int i = 0; i < P; ++i) ua[i] = czero<EC>();
-#pragma unroll
-      for (int c = 0; c < RAM; ++c) va[c] = czero<EC>();
       auto eig_a = [&](bool cold) __attribute__((always_inline)) {
         EC Ah[P * P];
 #pragma unroll
@@ -1050,56 +1150,59 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
           wave_sync();
           return;
         }
-        if (lane == 0) {
-#pragma unroll
-          for (int e = 0; e < P * P; ++e) {
-            sA[e] = tof(Ah[e]);
-            sAh[e] = Ah[e];
-          }
-        }
-        wave_sync();
-        float2 mrow[P];
-#pragma unroll
-        for (int j = 0; j < P; ++j) mrow[j] = sA[(lane < P ? lane : 0) * P + j];
-        group_subspace<RAM, 64, P, EC>(mrow, lane < P, r_a, va, sVa, cold, 500, PREC ? 1e-12 : 2e-6);
-        if (lane < P) {
+        // r_a > 1: every lane runs the same subspace iteration on Herm(A'),
+        // warm-started from the previous U_A (in LDS)
+        EC Vb[RAM][P];
+        if (!cold) {
 #pragma unroll
           for (int c = 0; c < RAM; ++c)
-            if (c < r_a) sUA[lane * RAM + c] = va[c];
+#pragma unroll
+            for (int i = 0; i < P; ++i) Vb[c][i] = sUA[i * RAM + c];
         }
         wave_sync();
-        // Hs = U^H Herm(A') U and A = U Hs U^H, reading U and Herm(A') from LDS
+        uniform_subspace<RAM, P, EC>([&](int i, int j) { return Ah[i * P + j]; }, r_a, Vb, cold, 500,
+                                     PREC ? 1e-12 : 2e-6);
+        if (lane == 0) {
+#pragma unroll
+          for (int c = 0; c < RAM; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+              if (c < r_a) sUA[i * RAM + c] = Vb[c][i];
+        }
+        // Hs = U^H Herm(A') U and A = U Hs U^H
         EC Hs[RAM][RAM];
 #pragma unroll
         for (int a = 0; a < RAM; ++a)
 #pragma unroll
           for (int b = 0; b < RAM; ++b) {
-            EC s = czero<EC>();
+            EC sacc = czero<EC>();
             if (a < r_a && b < r_a) {
+#pragma unroll
               for (int i = 0; i < P; ++i) {
                 EC t2 = czero<EC>();
-                for (int j = 0; j < P; ++j) t2 = cfma(sAh[i * P + j], sUA[j * RAM + b], t2);
-                s = ccfma(sUA[i * RAM + a], t2, s);
+#pragma unroll
+                for (int j = 0; j < P; ++j) t2 = cfma(Ah[i * P + j], Vb[b][j], t2);
+                sacc = ccfma(Vb[a][i], t2, sacc);
               }
             }
-            Hs[a][b] = s;
+            Hs[a][b] = sacc;
           }
         anorm2 = 0.f;
 #pragma unroll
         for (int i = 0; i < P; ++i)
 #pragma unroll
           for (int j = 0; j < P; ++j) {
-            EC s = czero<EC>();
+            EC sacc = czero<EC>();
 #pragma unroll
             for (int a = 0; a < RAM; ++a) {
               if (a >= r_a) continue;
               EC t2 = czero<EC>();
 #pragma unroll
               for (int b = 0; b < RAM; ++b)
-                if (b < r_a) t2 = cfma(Hs[a][b], cconj(sUA[j * RAM + b]), t2);
-              s = cfma(sUA[i * RAM + a], t2, s);
+                if (b < r_a) t2 = cfma(Hs[a][b], cconj(Vb[b][j]), t2);
+              sacc = cfma(Vb[a][i], t2, sacc);
             }
-            A[i * P + j] = tof(s);
+            A[i * P + j] = tof(sacc);
             anorm2 += cabs2(A[i * P + j]);
           }
         wave_sync();
@@ -1564,11 +1667,8 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
     for (int t = 0; t < NE; ++t) bv[t] = cz();
     EC ua[P];
-    EC va[RAM];
 #pragma unroll
     for (int i = 0; i < P; ++i) ua[i] = czero<EC>();
-#pragma unroll
-    for (int cc = 0; cc < RAM; ++cc) va[cc] = czero<EC>();
 
     if (!zero && !bad) {
       double resid = 0.0;
@@ -1645,50 +1745,60 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
           block_sync();   // sAh is rewritten by the next call
           return;
         }
-        float2 mrow[P];
+        // r_a > 1: every lane runs the same subspace iteration on Herm(A')
+        // (LDS), warm-started from the previous U_A
+        EC Vb[RAM][P];
+        if (!cold) {
 #pragma unroll
-        for (int j = 0; j < P; ++j) mrow[j] = sA[(lane < P ? lane : 0) * P + j];
-        group_subspace<RAM, 64, P, EC>(mrow, lane < P, r_a, va, sVa, cold, 500, PREC ? 1e-12 : 2e-6);
-        block_sync();
-        if (wave == 0 && lane < P) {
+          for (int c = 0; c < RAM; ++c)
 #pragma unroll
-          for (int cc = 0; cc < RAM; ++cc)
-            if (cc < r_a) sUA[lane * RAM + cc] = va[cc];
+            for (int i = 0; i < P; ++i) Vb[c][i] = sUA[i * RAM + c];
         }
-        block_sync();
+        uniform_subspace<RAM, P, EC>([&](int i, int j) { return sAh[i * P + j]; }, r_a, Vb, cold, 500,
+                                     PREC ? 1e-12 : 2e-6);
         EC Hs[RAM][RAM];
 #pragma unroll
         for (int a = 0; a < RAM; ++a)
 #pragma unroll
           for (int b = 0; b < RAM; ++b) {
-            EC s = czero<EC>();
+            EC sacc = czero<EC>();
             if (a < r_a && b < r_a) {
+#pragma unroll
               for (int i = 0; i < P; ++i) {
                 EC t2 = czero<EC>();
-                for (int j = 0; j < P; ++j) t2 = cfma(sAh[i * P + j], sUA[j * RAM + b], t2);
-                s = ccfma(sUA[i * RAM + a], t2, s);
+#pragma unroll
+                for (int j = 0; j < P; ++j) t2 = cfma(sAh[i * P + j], Vb[b][j], t2);
+                sacc = ccfma(Vb[a][i], t2, sacc);
               }
             }
-            Hs[a][b] = s;
+            Hs[a][b] = sacc;
           }
         anorm2 = 0.f;
 #pragma unroll
         for (int i = 0; i < P; ++i)
 #pragma unroll
           for (int j = 0; j < P; ++j) {
-            EC s = czero<EC>();
+            EC sacc = czero<EC>();
 #pragma unroll
             for (int a = 0; a < RAM; ++a) {
               if (a >= r_a) continue;
               EC t2 = czero<EC>();
 #pragma unroll
               for (int b = 0; b < RAM; ++b)
-                if (b < r_a) t2 = cfma(Hs[a][b], cconj(sUA[j * RAM + b]), t2);
-              s = cfma(sUA[i * RAM + a], t2, s);
+                if (b < r_a) t2 = cfma(Hs[a][b], cconj(Vb[b][j]), t2);
+              sacc = cfma(Vb[a][i], t2, sacc);
             }
-            A[i * P + j] = tof(s);
+            A[i * P + j] = tof(sacc);
             anorm2 += cabs2(A[i * P + j]);
           }
+        block_sync();   // every wave has read sUA and sAh
+        if (tid == 0) {
+#pragma unroll
+          for (int c = 0; c < RAM; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+              if (c < r_a) sUA[i * RAM + c] = Vb[c][i];
+        }
         block_sync();
       };
       // sweep 0 has no residual; after sweep k >= 1 the stop rule looks at
