@@ -470,12 +470,36 @@ __device__ __forceinline__ float2 bload(__amdgpu_buffer_rsrc_t r, uint32_t off) 
   return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 
+// Narrow kernels keep S in LDS as its upper q x q blocks S(i, j), i <= j, with
+// a padded row stride q + 1 (the lower blocks are their conjugate
+// transposes); block (i, j) starts at sblk(i, j).
+template <int P, int Q>
+__device__ __forceinline__ int sblk(int i, int j) {
+  return (i * P - i * (i - 1) / 2 + (j - i)) * Q * (Q + 1);
+}
+template <int P, int Q>
+__device__ __forceinline__ float2 sget(const float2* sS, int i, int j, int k, int l) {
+  if (i <= j) return sS[sblk<P, Q>(i, j) + k * (Q + 1) + l];
+  const float2 v = sS[sblk<P, Q>(j, i) + l * (Q + 1) + k];
+  return make_float2(v.x, -v.y);
+}
+// Stores element (a, b), a <= b, of the stacked pq x pq matrix (and, inside a
+// diagonal block, its mirror).  Only elements with a <= b are written, so
+// every position has exactly one writer.
+template <int P, int Q>
+__device__ __forceinline__ void sput(float2* sS, int a, int b, float2 v) {
+  const int ba = a / Q, ka = a - ba * Q, bb = b / Q, kb = b - bb * Q;
+  sS[sblk<P, Q>(ba, bb) + ka * (Q + 1) + kb] = v;
+  if (ba == bb) sS[sblk<P, Q>(ba, bb) + kb * (Q + 1) + ka] = make_float2(v.x, -v.y);
+}
+
 // ------------------------------------------------------------ a2, FP32
 // S = (1/n) sum_m x_m x_m^H of one pixel on v_mfma_f32_16x16x4_f32, written
 // to LDS as the full Hermitian pq x pq matrix (row-major).
 template <int P, int Q>
 __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint32_t rec, const uint32_t* sOffB,
-                                         const uint32_t (&loff)[(P * Q + 15) / 16], int n, float2* sS) {
+                                         const uint32_t (&loff)[(P * Q + 15) / 16], int n, float2* sS,
+                                         float* sP) {
   constexpr int PQ = P * Q;
   constexpr int NB = (PQ + 15) / 16;
   constexpr int NT = NB * (NB + 1) / 2;
@@ -566,10 +590,17 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
     for (int sl = 0; sl < PF - 1; ++sl)
       if (ch0 + sl < nch) accumulate(ring[sl]);
 
-    // S to LDS, full Hermitian, scaled by 1/n.  MFMA output layout: lane l,
+    // S to LDS (upper blocks), scaled by 1/n.  MFMA output layout: lane l,
     // register q holds row 4*(l/16) + q, column l % 16 of the 16 x 16 tile.
+    // Im of a diagonal tile is P - P^T with P = Xi Xr^T: the raw P goes through
+    // the scratch sP ([NB][16][16]) for the transposed element.
     const float inv_n = 1.f / float(n);
     const int trow = 4 * (lane >> 4), tcol = lane & 15;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) sP[(I * 16 + trow + q4) * 16 + tcol] = accD[I][q4];
+    wave_sync();
     {
       int t = 0, u = 0;
 #pragma unroll
@@ -579,15 +610,11 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
 #pragma unroll
           for (int q4 = 0; q4 < 4; ++q4) {
             const int row = 16 * I + trow + q4, col = 16 * J + tcol;
-            if (row < PQ && col < PQ) {
+            if (row < PQ && col < PQ && row <= col) {
               const float re = accR[t][q4] * inv_n;
-              if (J > I) {
-                const float im = accI[u][q4] * inv_n;
-                sS[row * PQ + col] = make_float2(re, im);
-                sS[col * PQ + row] = make_float2(re, -im);
-              } else {
-                sS[row * PQ + col] = make_float2(re, accD[I][q4] * inv_n);
-              }
+              const float im = (J > I) ? accI[u][q4] * inv_n
+                                       : (accD[I][q4] - sP[(I * 16 + tcol) * 16 + trow + q4]) * inv_n;
+              sput<P, Q>(sS, row, col, make_float2(re, im));
             }
           }
           if (J > I) ++u;
@@ -596,26 +623,6 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
       }
     }
     wave_sync();
-    {
-      float tr_[NB][4];
-#pragma unroll
-      for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          const int row = 16 * I + trow + q4, col = 16 * I + tcol;
-          tr_[I][q4] = (row < PQ && col < PQ) ? sS[col * PQ + row].y : 0.f;
-        }
-      wave_sync();
-#pragma unroll
-      for (int I = 0; I < NB; ++I)
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4) {
-          const int row = 16 * I + trow + q4, col = 16 * I + tcol;
-          if (row < PQ && col < PQ) sS[row * PQ + col].y = accD[I][q4] * inv_n - tr_[I][q4];
-        }
-    }
-    wave_sync();
-
 }
 
 // -------------------------------------------------------- a2, split BF16
@@ -755,11 +762,8 @@ __device__ __forceinline__ void scm_bf16x3(const uint32_t* hwin, const uint32_t*
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4) {
         const int row = 16 * I + trow + q4, col = 16 * J + tcol;
-        if (row < PQ && col < PQ) {
-          const float re = accR[t][q4] * inv_n, im = accI[t][q4] * inv_n;
-          sS[row * PQ + col] = make_float2(re, im);
-          if (J > I) sS[col * PQ + row] = make_float2(re, -im);
-        }
+        if (row < PQ && col < PQ && row <= col)
+          sput<P, Q>(sS, row, col, make_float2(accR[t][q4] * inv_n, accI[t][q4] * inv_n));
       }
   wave_sync();
 }
@@ -783,14 +787,19 @@ struct Lds {
   static constexpr int PQ = P * Q;
   static constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
   static constexpr int G = Groups<Q>::G;
-  static constexpr bool kTailInS = sizeof(EC) * RBM * Q * G <= sizeof(float2) * PQ * PQ;
+  static constexpr int NB = (PQ + 15) / 16;
+  // B / tail / transpose scratch: the raw time factor B (q x q), the batched
+  // tail's basis exchange, and the FP32 path's diagonal-tile transpose
+  static constexpr size_t kB = sizeof(float2) * Q * Q;
+  static constexpr size_t kT = sizeof(EC) * RBM * Q * G;
+  static constexpr size_t kP = PREC ? 0 : sizeof(float) * NB * 256;
+  static constexpr size_t kBT = kB > kT ? (kB > kP ? kB : kP) : (kT > kP ? kT : kP);
   static constexpr size_t oUA = 0;                                        // EC[P*RAM]
   static constexpr size_t oAh = oUA + sizeof(EC) * P * RAM;               // EC[P*P]
-  static constexpr size_t oVa = oAh + sizeof(EC) * P * P;                 // EC[P*RAM]
-  static constexpr size_t oQUA = oVa + sizeof(EC) * P * RAM;              // EC[G][P*RAM]
-  static constexpr size_t oVt = oQUA + sizeof(EC) * G * P * RAM;          // EC[RBM*Q*G] unless in S
-  static constexpr size_t oS = oVt + (kTailInS ? 0 : sizeof(EC) * RBM * Q * G);   // float2[PQ*PQ]
-  static constexpr size_t oA = oS + sizeof(float2) * PQ * PQ;             // float2[P*P]
+  static constexpr size_t oQUA = oAh + sizeof(EC) * P * P;                // EC[G][P*RAM]
+  static constexpr size_t oBT = oQUA + sizeof(EC) * G * P * RAM;          // kBT bytes
+  static constexpr size_t oS = (oBT + kBT + 15) / 16 * 16;                // float2[P(P+1)/2][Q][Q+1]
+  static constexpr size_t oA = oS + sizeof(float2) * (P * (P + 1) / 2) * Q * (Q + 1);   // float2[P*P]
   static constexpr size_t oQidx = oA + sizeof(float2) * P * P;            // int64[G]
   static constexpr size_t oOff = oQidx + sizeof(int64_t) * G;             // uint32[kMaxN + kOffPad]
   static constexpr size_t oQflag = oOff + sizeof(uint32_t) * (kMaxN + kOffPad);   // int[G]
@@ -814,16 +823,15 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   constexpr int RAM = L::RAM;
   constexpr int QP = Groups<Q>::QP;         // lanes per pixel in the batched tail
   constexpr int G = Groups<Q>::G;           // pixels per batched tail
-  static_assert(PQ * PQ >= QQ, "LDS reuse");
 
-  float2* const sS = reinterpret_cast<float2*>(lds + L::oS);     // S; then raw B; then tail scratch
+  float2* const sS = reinterpret_cast<float2*>(lds + L::oS);     // S, upper blocks
+  float2* const sBT = reinterpret_cast<float2*>(lds + L::oBT);   // raw B, then tail scratch
   uint32_t* const sOffB = reinterpret_cast<uint32_t*>(lds + L::oOff);
   float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
   EC* const sUA = reinterpret_cast<EC*>(lds + L::oUA);
   EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
-  EC* const sVa = reinterpret_cast<EC*>(lds + L::oVa);
   EC (*const sQUA)[P * RAM] = reinterpret_cast<EC (*)[P * RAM]>(lds + L::oQUA);   // queued pixels: U_A
-  EC* const tail_scratch = L::kTailInS ? reinterpret_cast<EC*>(sS) : reinterpret_cast<EC*>(lds + L::oVt);
+  EC* const tail_scratch = reinterpret_cast<EC*>(sBT);
   int64_t* const sQidx = reinterpret_cast<int64_t*>(lds + L::oQidx);             //   pixel index
   int* const sQflag = reinterpret_cast<int*>(lds + L::oQflag);                   //   0 ok, 1 zero, 2 non-finite
   float* const sQeta = reinterpret_cast<float*>(lds + L::oQeta);
@@ -1011,7 +1019,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 
     // ---------------------------------------------------------------- a2 SCM
     if constexpr (PREC == 0)
-      scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS);
+      scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS, reinterpret_cast<float*>(sBT));
     else
       scm_bf16x3<P, Q>(prm.xs + win, prm.xs + P * plane + win, plane, prm.rec_bytes / 2, sOffB, loff, n, sS);
 
@@ -1032,7 +1040,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
           for (int i = 0; i < P; ++i)
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-              const float2 s = sS[(i * Q + k) * PQ + j * Q + l];
+              const float2 s = sget<P, Q>(sS, i, j, k, l);
               a0[i * P + j] = cadd(a0[i * P + j], s);
               if (k == l) pt[i * P + j] = cadd(pt[i * P + j], s);
               nr += cabs2(s);
@@ -1086,7 +1094,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 #pragma unroll
             for (int i = 0; i < P; ++i)
 #pragma unroll
-              for (int j = 0; j < P; ++j) s[i * P + j] = sS[(i * Q + k) * PQ + j * Q + l];
+              for (int j = 0; j < P; ++j) s[i * P + j] = sget<P, Q>(sS, i, j, k, l);
             if (res) {
               float acc = 0.f;
 #pragma unroll
@@ -1150,8 +1158,10 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
           wave_sync();
           return;
         }
-        // r_a > 1: every lane runs the same subspace iteration on Herm(A'),
-        // warm-started from the previous U_A (in LDS)
+        // r_a > 1: the top-r_a subspace of Herm(A'), warm-started from the
+        // previous U_A (in LDS).  p <= 4: every lane runs the same subspace
+        // iteration with no cross-lane traffic; larger p: lane k holds row k
+        // and the dot products are wave reductions (fewer registers).
         EC Vb[RAM][P];
         if (!cold) {
 #pragma unroll
@@ -1160,8 +1170,39 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
             for (int i = 0; i < P; ++i) Vb[c][i] = sUA[i * RAM + c];
         }
         wave_sync();
-        uniform_subspace<RAM, P, EC>([&](int i, int j) { return Ah[i * P + j]; }, r_a, Vb, cold, 500,
-                                     PREC ? 1e-12 : 2e-6);
+        if constexpr (P <= 4) {
+          uniform_subspace<RAM, P, EC>([&](int i, int j) { return Ah[i * P + j]; }, r_a, Vb, cold, 500,
+                                       PREC ? 1e-12 : 2e-6);
+        } else {
+          if (lane == 0) {
+#pragma unroll
+            for (int e = 0; e < P * P; ++e) sA[e] = tof(Ah[e]);
+          }
+          wave_sync();
+          float2 mrow[P];
+#pragma unroll
+          for (int j = 0; j < P; ++j) mrow[j] = sA[(lane < P ? lane : 0) * P + j];
+          EC va[RAM];
+#pragma unroll
+          for (int c = 0; c < RAM; ++c) {
+            EC sel = czero<EC>();
+#pragma unroll
+            for (int i = 0; i < P; ++i) sel = (i == lane) ? Vb[c][i] : sel;
+            va[c] = sel;
+          }
+          group_subspace<RAM, 64, P, EC>(mrow, lane < P, r_a, va, sAh, cold, 500, PREC ? 1e-12 : 2e-6);
+          // every lane gathers the whole basis from LDS
+          if (lane < P) {
+#pragma unroll
+            for (int c = 0; c < RAM; ++c) sUA[lane * RAM + c] = va[c];
+          }
+          wave_sync();
+#pragma unroll
+          for (int c = 0; c < RAM; ++c)
+#pragma unroll
+            for (int i = 0; i < P; ++i) Vb[c][i] = sUA[i * RAM + c];
+          wave_sync();
+        }
         if (lane == 0) {
 #pragma unroll
           for (int c = 0; c < RAM; ++c)
@@ -1231,12 +1272,12 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = lane + 64 * t;
-      if (e < QQ) sS[e] = bv[t];   // B[k][l] at k*q + l
+      if (e < QQ) sBT[e] = bv[t];   // B[k][l] at k*q + l
     }
     wave_sync();
     if (tg == nq && tk < Q) {
 #pragma unroll
-      for (int l = 0; l < Q; ++l) Bq[l] = cscale(cadd(sS[tk * Q + l], cconj(sS[l * Q + tk])), 0.5f);
+      for (int l = 0; l < Q; ++l) Bq[l] = cscale(cadd(sBT[tk * Q + l], cconj(sBT[l * Q + tk])), 0.5f);
     }
     if (lane == 0) {
       sQidx[nq] = idx;
