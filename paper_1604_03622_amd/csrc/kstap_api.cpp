@@ -350,6 +350,26 @@ stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out) {
     pl->dc_min = std::min(pl->dc_min, pl->stencil[2 * m + 1]);
     pl->dc_max = std::max(pl->dc_max, pl->stencil[2 * m + 1]);
   }
+  {
+    // one-pixel move to the right: o enters if o is in the stencil and
+    // o + (0, 1) is not; o leaves if o + (0, 1) is in the stencil and o is not
+    std::set<std::pair<int, int>> st;
+    for (int m = 0; m < c.n; ++m) st.insert({pl->stencil[2 * m], pl->stencil[2 * m + 1]});
+    for (const auto& o : st) {
+      if (!st.count({o.first, o.second + 1})) {
+        pl->dadd.push_back(o.first);
+        pl->dadd.push_back(o.second);
+      }
+      if (!st.count({o.first, o.second - 1})) {
+        pl->drem.push_back(o.first);
+        pl->drem.push_back(o.second - 1);
+      }
+    }
+    if (pl->dadd.size() > 2 * size_t(kstap::kMaxDelta) || pl->drem.size() > 2 * size_t(kstap::kMaxDelta)) {
+      pl->dadd.clear();
+      pl->drem.clear();
+    }
+  }
   pl->b_steer.assign(2 * c.q, 0.f);
   for (int j = 0; j < c.q; ++j) {
     pl->b_steer[2 * j] = c.b_steer ? c.b_steer[2 * j] : 1.f;
@@ -431,9 +451,11 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
   k.T = T;
   k.D = D;
   const int64_t total = kstap::tiled_positions(H, W);
-  // enough workgroups to cover 256 CUs several times over, at most 16 pixels each
+  // enough workgroups to cover 256 CUs several times over, 4 to 16 positions
+  // each (a multiple of 4: runs start on a unit row, see the sliding window)
   int64_t ppb = total / (256 * 8 * 4);
-  ppb = std::max<int64_t>(1, std::min<int64_t>(16, ppb));
+  ppb = std::max<int64_t>(4, std::min<int64_t>(16, ppb));
+  ppb = (ppb + 3) / 4 * 4;
   k.pix_per_block = int32_t(ppb);
   k.nlogical = int32_t((total + ppb - 1) / ppb);
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -556,7 +578,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
   b->ppb = 16;
   b->grid_mult = 1;
   if (pix_per_item > 0) {
-    b->ppb = pix_per_item;
+    b->ppb = (pix_per_item + 3) / 4 * 4;   // runs start on a unit row
   } else {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(b->signature);

@@ -625,6 +625,105 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
     wave_sync();
 }
 
+// Sliding-window update of S (FP32): from the left neighbour's S (in LDS),
+// n S += sum over entering vectors x x^H - sum over leaving ones.  sAdd /
+// sRem: byte offsets (kOut past nadd / nrem and for 8 entries beyond).
+// Diagonal tiles take both Im products here (no transpose through LDS), so
+// the reloaded antisymmetric part stays exact.
+template <int P, int Q>
+__device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane, uint32_t rec,
+                                               const uint32_t* sAdd, int nadd, const uint32_t* sRem, int nrem,
+                                               const uint32_t (&loff)[(P * Q + 15) / 16], int n, float2* sS) {
+  constexpr int PQ = P * Q;
+  constexpr int NB = (PQ + 15) / 16;
+  constexpr int NT = NB * (NB + 1) / 2;
+  constexpr int NO = NB * (NB - 1) / 2;
+  const int lane = threadIdx.x;
+  const int trow = 4 * (lane >> 4), tcol = lane & 15;
+  const float fn = float(n);
+  f4 accR[NT], accI[NO > 0 ? NO : 1], accD[NB];
+  {
+    int t = 0, u = 0;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = I; J < NB; ++J) {
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int row = 16 * I + trow + q4, col = 16 * J + tcol;
+          float2 v = make_float2(0.f, 0.f);
+          if (row < PQ && col < PQ) v = sget<P, Q>(sS, row / Q, col / Q, row % Q, col % Q);
+          accR[t][q4] = v.x * fn;
+          if (J > I) accI[u][q4] = v.y * fn;
+          else accD[I][q4] = v.y * fn;
+        }
+        if (J > I) ++u;
+        ++t;
+      }
+  }
+  __amdgpu_buffer_rsrc_t rs[NB];
+#pragma unroll
+  for (int I = 0; I < NB; ++I) rs[I] = block_rsrc<Q>(xwin, plane, rec, I);
+#pragma unroll 1
+  for (int pass = 0; pass < 2; ++pass) {
+    const uint32_t* tab = pass ? sRem : sAdd;
+    const int cnt = pass ? nrem : nadd;
+    const float sg = pass ? -1.f : 1.f;
+#pragma unroll 1
+    for (int ch = 0; ch < (cnt + 3) >> 2; ++ch) {
+      const uint32_t off = tab[ch * 4 + (lane >> 4)];
+      float2 v[NB];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) v[I] = bload(rs[I], loff[I] + off);
+      float xr[NB], xi[NB], sxr[NB], sxi[NB], nsxr[NB];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) {
+        xr[I] = v[I].x;
+        xi[I] = v[I].y;
+        sxr[I] = sg * v[I].x;
+        sxi[I] = sg * v[I].y;
+        nsxr[I] = -sxr[I];
+      }
+      int t = 0, u = 0;
+#pragma unroll
+      for (int I = 0; I < NB; ++I)
+#pragma unroll
+        for (int J = I; J < NB; ++J) {
+          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sxr[I], xr[J], accR[t], 0, 0, 0);
+          accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(sxi[I], xi[J], accR[t], 0, 0, 0);
+          if (J > I) {
+            accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(sxi[I], xr[J], accI[u], 0, 0, 0);
+            accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(nsxr[I], xi[J], accI[u], 0, 0, 0);
+            ++u;
+          } else {
+            accD[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(sxi[I], xr[I], accD[I], 0, 0, 0);
+            accD[I] = __builtin_amdgcn_mfma_f32_16x16x4f32(nsxr[I], xi[I], accD[I], 0, 0, 0);
+          }
+          ++t;
+        }
+    }
+  }
+  wave_sync();   // every lane has reloaded its part of the old S
+  const float inv_n = 1.f / fn;
+  {
+    int t = 0, u = 0;
+#pragma unroll
+    for (int I = 0; I < NB; ++I)
+#pragma unroll
+      for (int J = I; J < NB; ++J) {
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4) {
+          const int row = 16 * I + trow + q4, col = 16 * J + tcol;
+          if (row < PQ && col < PQ && row <= col)
+            sput<P, Q>(sS, row, col, make_float2(accR[t][q4] * inv_n, ((J > I) ? accI[u][q4] : accD[I][q4]) * inv_n));
+        }
+        if (J > I) ++u;
+        ++t;
+      }
+  }
+  wave_sync();
+}
+
 // -------------------------------------------------------- a2, split BF16
 // The same S from three BF16 products per tile: x = hi + lo with
 // hi = bf16(x), lo = bf16(x - hi); S ~ hi hi^H + hi lo^H + lo hi^H with FP32
@@ -802,7 +901,8 @@ struct Lds {
   static constexpr size_t oA = oS + sizeof(float2) * (P * (P + 1) / 2) * Q * (Q + 1);   // float2[P*P]
   static constexpr size_t oQidx = oA + sizeof(float2) * P * P;            // int64[G]
   static constexpr size_t oOff = oQidx + sizeof(int64_t) * G;             // uint32[kMaxN + kOffPad]
-  static constexpr size_t oQflag = oOff + sizeof(uint32_t) * (kMaxN + kOffPad);   // int[G]
+  static constexpr size_t oDelta = oOff + sizeof(uint32_t) * (kMaxN + kOffPad);   // uint32[2][kMaxDelta + 8]
+  static constexpr size_t oQflag = oDelta + sizeof(uint32_t) * 2 * (kMaxDelta + 8);   // int[G]
   static constexpr size_t oQit = oQflag + sizeof(int) * G;                // int[G]
   static constexpr size_t oQeta = oQit + sizeof(int) * G;                 // float[G]
   static constexpr size_t bytes = ((oQeta + sizeof(float) * G) + 15) / 16 * 16;
@@ -827,6 +927,8 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   float2* const sS = reinterpret_cast<float2*>(lds + L::oS);     // S, upper blocks
   float2* const sBT = reinterpret_cast<float2*>(lds + L::oBT);   // raw B, then tail scratch
   uint32_t* const sOffB = reinterpret_cast<uint32_t*>(lds + L::oOff);
+  uint32_t* const sAdd = reinterpret_cast<uint32_t*>(lds + L::oDelta);   // sliding window: entering
+  uint32_t* const sRem = sAdd + kMaxDelta + 8;                            //   and leaving vectors
   float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
   EC* const sUA = reinterpret_cast<EC*>(lds + L::oUA);
   EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
@@ -849,6 +951,12 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   for (int m = lane; m < kMaxN + kOffPad; m += 64)
     sOffB[m] = (m < n) ? uint32_t(((int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q - prm.st_min) * kSample)
                        : kOut;
+  for (int m = lane; m < kMaxDelta + 8; m += 64) {
+    sAdd[m] = (m < prm.nadd) ? uint32_t(((int(prm.dadd[2 * m]) * W + int(prm.dadd[2 * m + 1])) * Q - prm.st_min) * kSample)
+                             : kOut;
+    sRem[m] = (m < prm.nrem) ? uint32_t(((int(prm.drem[2 * m]) * W + int(prm.drem[2 * m + 1])) * Q - prm.st_min) * kSample)
+                             : kOut;
+  }
   wave_sync();
 
   // Operand rows of this lane: row rho = 16*I + (lane & 15) of the stacked
@@ -985,9 +1093,16 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     wave_sync();
   };
 
+  // Sliding window (run mode, FP32 path): a pixel at column 1..3 of its 4x4
+  // unit row updates its left neighbour's S when this workgroup has just
+  // computed it from finite data; columns 0 start from the full sum.  Runs
+  // start on a unit row, so the choice is the same for every decomposition.
+  bool chain = false;
   for (int64_t it = 0; it < count; ++it) {
     int64_t idx;
     int r, c;
+    const bool left_ok = chain;
+    chain = false;
     if (MODE == kModeRun) {
       if (!tiled_pixel(first + it, H, W, &r, &c)) continue;
       idx = int64_t(r) * W + c;
@@ -1018,10 +1133,17 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     const int64_t win = (int64_t(r) * W + c) * Q + prm.st_min;
 
     // ---------------------------------------------------------------- a2 SCM
-    if constexpr (PREC == 0)
-      scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS, reinterpret_cast<float*>(sBT));
-    else
+    // (the mixed path is bound by its FP64 solves, not by the cheaper BF16
+    // MFMAs, so it always takes the full sum)
+    const bool slide = PREC == 0 && MODE == kModeRun && left_ok && ((first + it) & 3) != 0 && prm.nadd >= 0;
+    if constexpr (PREC == 0) {
+      if (slide)
+        scm_fp32_delta<P, Q>(prm.x + win, plane, prm.rec_bytes, sAdd, prm.nadd, sRem, prm.nrem, loff, n, sS);
+      else
+        scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS, reinterpret_cast<float*>(sBT));
+    } else {
       scm_bf16x3<P, Q>(prm.xs + win, prm.xs + P * plane + win, plane, prm.rec_bytes / 2, sOffB, loff, n, sS);
+    }
 
     // ------------------------------------------------ a4 init, ||R||_F = ||S||_F
     float2 A[P * P];
@@ -1063,6 +1185,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     int iters = 0;
     const bool zero = !(normR2 > 0.0);
     const bool bad = !isfinite(normR2);
+    chain = !bad;   // this S may seed the right neighbour's
     float2 bv[NE];
 #pragma unroll
     for (int t = 0; t < NE; ++t) bv[t] = cz();

@@ -12,6 +12,7 @@ constexpr int kMaxQ = 32;
 constexpr int kMaxN = 256;
 constexpr int kMaxRA = 4;
 constexpr int kMaxRB = 8;
+constexpr int kMaxDelta = 48;   // training vectors entering (or leaving) on a one-pixel move
 
 // Everything a launch needs, passed by value as the kernel argument
 // (about 1.6 KB; the kernarg segment allows 4 KB).
@@ -45,7 +46,15 @@ struct KParams {
   float2 b_s[kMaxQ];
   float2 h_s[kMaxP];
   int16_t st[2 * kMaxN];  // stencil (dr, dc)
+  // sliding-window update (run mode): from the left neighbour's S, add the
+  // nadd vectors dadd and remove the nrem vectors drem, offsets relative to
+  // the pixel; nadd < 0: always the full sum
+  int32_t nadd, nrem;
+  int16_t dadd[2 * kMaxDelta];
+  int16_t drem[2 * kMaxDelta];
 };
+
+static_assert(sizeof(KParams) <= 4096, "KParams is passed as a kernel argument");
 
 enum Mode { kModeRun = 0, kModeProbe = 1 };
 

@@ -155,8 +155,10 @@ def test_probe_subspaces_and_iterations():
     g = ref["valid"] & (oracle.relative_gaps(ref["lam_B"], 3) >= 1e-3)
     T_probe = pr["T"].cpu().numpy()
     assert rel_err(T_probe[g], ref["T"][g]).max() <= TOL
-    # the probe runs the same body as the frame pass: identical results
-    np.testing.assert_array_equal(T_probe, T_run.cpu().numpy()[pix[:, 0], pix[:, 1]])
+    # the probe runs the frame pass's body on single pixels; the frame pass
+    # may update a left neighbour's covariance instead of summing all n
+    # vectors, which changes only the FP32 summation order
+    assert rel_err(T_probe, T_run.cpu().numpy()[pix[:, 0], pix[:, 1]]).max() <= 2e-5
     UA = pr["U_A"].cpu().numpy().astype(np.complex128)
     UB = pr["U_B"].cpu().numpy().astype(np.complex128)
     PA = UA @ np.conj(np.swapaxes(UA, 1, 2))
