@@ -129,6 +129,20 @@ __device__ __forceinline__ double wsumd(double v) {
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }   // one-wave workgroups
 
+// LDS exchange among the lanes of one wavefront inside a workgroup of several:
+// a wavefront's LDS operations are performed in issue order, so only the
+// compiler has to be kept from moving accesses across this point.
+__device__ __forceinline__ void lane_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <bool WAVE_LOCAL>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE_LOCAL) lane_sync();
+  else wave_sync();
+}
+
 __device__ __forceinline__ float frac01(float x) { return x - floorf(x); }
 
 // Deterministic, generic start block for subspace iteration.
@@ -208,8 +222,10 @@ __device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
 // when ||M V - V (V^H M V)||_F <= tol ||M V||_F for the basis entering a step;
 // that step's orthonormalised M V is kept and the group's basis is frozen.
 // The loop runs until every group has converged or max_steps; each group's
-// result is the one it would reach alone.  sV: LDS scratch of RM * D * (64 / QP) float2.
-template <int RM, int QP, int D, typename C>
+// result is the one it would reach alone.  sV: LDS scratch of RM * D * (64 / QP) C
+// for this wavefront.  WAVE_LOCAL: the wavefront shares its workgroup with
+// others that run their own solves, so it synchronises only its own lanes.
+template <int RM, int QP, int D, typename C, bool WAVE_LOCAL = false>
 __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_ok, int r, C (&v)[RM],
                                               C* sV, bool cold, int max_steps, double tol) {
   using S = decltype(C{}.x);
@@ -228,7 +244,7 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
       for (int c = 0; c < RM; ++c)
         if (c < r) sV[(c * D + k) * G + g] = v[c];
     }
-    wave_sync();
+    lds_sync<WAVE_LOCAL>();
     C w[RM];
 #pragma unroll
     for (int c = 0; c < RM; ++c) w[c] = czero<C>();
@@ -245,7 +261,7 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
           if (c < r) w[c] = cfma(mc, sV[(c * D + l) * G + g], w[c]);
       }
     }
-    wave_sync();
+    lds_sync<WAVE_LOCAL>();
     bool conv = false;
     if (tested) {
       // residual W - V (V^H W), one column at a time
@@ -877,6 +893,137 @@ struct Groups {
 template <bool B, typename T, typename F> struct Pick { using type = T; };
 template <typename T, typename F> struct Pick<false, T, F> { using type = F; };
 
+// ------------------------------------------------ a6 + a8, batched
+// Top-r_b time subspace, projected test vector and statistic for up to
+// 64 / QP queued pixels of one wavefront: lane group `slot` (QP lanes) serves
+// queue slot `slot`, whose lane k holds row k of the pixel's Hermitian time
+// factor in Bq; slots >= nfill are empty.  Per slot the queue holds the pixel
+// index, a flag (0 ok, 1 zero covariance, 2 non-finite), eta, the iteration
+// count and U_A (p x RAM).  Writes T (and D, or the probe outputs).
+// WAVE_LOCAL: other wavefronts of the workgroup run their own tails.
+template <int P, int Q, int RBM, int MODE, typename EC, bool WAVE_LOCAL>
+__device__ __forceinline__ void tail_batch(const KParams& prm, const float2 (&Bq)[Q], int slot, int nfill,
+                                           const int* sQflag, const int64_t* sQidx, const float* sQeta,
+                                           const int* sQit, const EC (*sQUA)[P * ((P < kMaxRA) ? P : kMaxRA)],
+                                           EC* scratch, double tol) {
+  using ES = decltype(EC{}.x);
+  constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
+  constexpr int QP = Groups<Q>::QP;
+  const int tk = (threadIdx.x & 63) % QP;
+  const int H = prm.H, W = prm.W;
+  const int r_a = prm.r_a, r_b = prm.r_b;
+  const bool slot_ok = slot < nfill;
+  const bool rok = slot_ok && tk < Q;
+  const int flag = slot_ok ? sQflag[slot] : 1;
+  const int64_t pidx = slot_ok ? sQidx[slot] : 0;
+  EC vb[RBM];
+#pragma unroll
+  for (int c = 0; c < RBM; ++c) vb[c] = czero<EC>();
+  if (r_b > 0)
+    group_subspace<RBM, QP, Q, EC, WAVE_LOCAL>(Bq, rok && flag == 0, r_b, vb, scratch, true, 200, tol);
+  // statistic
+  int pr, pc;
+  if (MODE == kModeRun) {
+    pr = int(pidx / W);
+    pc = int(pidx - int64_t(pr) * W);
+  } else {
+    pr = prm.pix[2 * pidx];
+    pc = prm.pix[2 * pidx + 1];
+  }
+  const bool use = rok && flag == 0;
+  const EC bsk = use ? cto<EC>(prm.b_s[tk]) : czero<EC>();
+  EC gk = bsk;
+  if (r_b > 0) {
+#pragma unroll
+    for (int c = 0; c < RBM; ++c) {
+      if (c >= r_b) continue;
+      const EC coef = gsum<QP>(ccfma(vb[c], bsk, czero<EC>()));
+      if (use) gk = csub(gk, cmul(vb[c], coef));
+    }
+  }
+  const float2* xt = prm.x + (int64_t(pr) * W + pc) * Q;
+  EC w[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const EC xv = use ? cto<EC>(xt[int64_t(i) * H * W * Q + tk]) : czero<EC>();
+    w[i] = gsum<QP>(cmul(xv, cconj(gk)));
+  }
+  const ES den = gsum<QP>(ES(bsk.x * gk.x + bsk.y * gk.y));
+  const EC* Uq = sQUA[slot_ok ? slot : 0];   // U_A of the queued pixel, p x RAM
+  EC z[P];
+  {
+    EC cw[RAM];
+#pragma unroll
+    for (int c = 0; c < RAM; ++c) {
+      cw[c] = czero<EC>();
+      if (c < r_a) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) cw[c] = ccfma(Uq[i * RAM + c], w[i], cw[c]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      z[i] = w[i];
+#pragma unroll
+      for (int c = 0; c < RAM; ++c)
+        if (c < r_a) z[i] = csub(z[i], cmul(Uq[i * RAM + c], cw[c]));
+    }
+  }
+  const bool den_ok = den > ES(1e-12) * ES(prm.bs_norm2);
+  float T;
+  if (prm.stat_mode == 0) {
+    ES num = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) num += cabs2(z[i]);
+    T = den_ok ? float(num / den) : 0.f;
+  } else {
+    EC hz = czero<EC>(), fh[P], hs[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) fh[i] = hs[i] = cto<EC>(prm.h_s[i]);
+#pragma unroll
+    for (int c = 0; c < RAM; ++c) {
+      if (c >= r_a) continue;
+      EC ch = czero<EC>();
+#pragma unroll
+      for (int i = 0; i < P; ++i) ch = ccfma(Uq[i * RAM + c], hs[i], ch);
+#pragma unroll
+      for (int i = 0; i < P; ++i) fh[i] = csub(fh[i], cmul(Uq[i * RAM + c], ch));
+    }
+    ES hfh = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      hz = ccfma(hs[i], z[i], hz);
+      hfh += hs[i].x * fh[i].x + hs[i].y * fh[i].y;
+    }
+    const bool ok = den_ok && hfh > ES(1e-12) * ES(prm.h_norm2);
+    T = ok ? float(cabs2(hz) / (hfh * den)) : 0.f;
+  }
+  if (!isfinite(T)) T = NAN;
+  if (flag == 1) T = 0.f;
+  if (flag == 2) T = NAN;
+  if (slot_ok && tk == 0) {
+    prm.T[pidx] = T;
+    if (MODE == kModeRun && prm.D) prm.D[pidx] = (T > prm.tau) ? 1 : 0;
+    if (MODE == kModeProbe) {
+      if (prm.eta) prm.eta[pidx] = sQeta[slot];
+      if (prm.iters) prm.iters[pidx] = sQit[slot];
+    }
+  }
+  if (MODE == kModeProbe && slot_ok) {
+    if (prm.UA && tk < P) {
+#pragma unroll
+      for (int c = 0; c < RAM; ++c)
+        if (c < r_a) prm.UA[(pidx * P + tk) * r_a + c] = (flag != 0) ? cz() : tof(sQUA[slot][tk * RAM + c]);
+    }
+    if (prm.UB && tk < Q) {
+#pragma unroll
+      for (int c = 0; c < RBM; ++c)
+        if (c < r_b) prm.UB[(pidx * Q + tk) * r_b + c] = (flag != 0) ? cz() : tof(vb[c]);
+    }
+  }
+  lds_sync<WAVE_LOCAL>();
+}
+
 // PREC 0: FP32 covariance, FP32 eigensolves and statistic.
 // PREC 1: split-BF16 covariance, FP64 eigensolves and statistic.
 // LDS carve-out of one pixel pipeline (one workgroup), largest alignment first.
@@ -981,116 +1128,8 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 
   // ------------------------------------------------ a6 + a8 for G pixels
   auto tail = [&](int nfill) __attribute__((always_inline)) {
-    const bool slot_ok = tg < nfill;
-    const bool rok = slot_ok && tk < Q;
-    const int flag = slot_ok ? sQflag[tg] : 1;
-    const int64_t pidx = slot_ok ? sQidx[tg] : 0;
-    EC vb[RBM];
-#pragma unroll
-    for (int c = 0; c < RBM; ++c) vb[c] = czero<EC>();
-    if (r_b > 0)
-      group_subspace<RBM, QP, Q, EC>(Bq, rok && flag == 0, r_b, vb, tail_scratch, true, 200, PREC ? 1e-12 : 2e-6);
-    // statistic
-    int pr, pc;
-    if (MODE == kModeRun) {
-      pr = int(pidx / W);
-      pc = int(pidx - int64_t(pr) * W);
-    } else {
-      pr = prm.pix[2 * pidx];
-      pc = prm.pix[2 * pidx + 1];
-    }
-    const bool use = rok && flag == 0;
-    const EC bsk = use ? cto<EC>(prm.b_s[tk]) : czero<EC>();
-    EC gk = bsk;
-    if (r_b > 0) {
-#pragma unroll
-      for (int c = 0; c < RBM; ++c) {
-        if (c >= r_b) continue;
-        const EC coef = gsum<QP>(ccfma(vb[c], bsk, czero<EC>()));
-        if (use) gk = csub(gk, cmul(vb[c], coef));
-      }
-    }
-    const float2* xt = prm.x + (int64_t(pr) * W + pc) * Q;
-    EC w[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const EC xv = use ? cto<EC>(xt[int64_t(i) * H * W * Q + tk]) : czero<EC>();
-      w[i] = gsum<QP>(cmul(xv, cconj(gk)));
-    }
-    const ES den = gsum<QP>(ES(bsk.x * gk.x + bsk.y * gk.y));
-    const EC* Uq = sQUA[slot_ok ? tg : 0];   // U_A of the queued pixel, p x RAM
-    EC z[P];
-    {
-      EC cw[RAM];
-#pragma unroll
-      for (int c = 0; c < RAM; ++c) {
-        cw[c] = czero<EC>();
-        if (c < r_a) {
-#pragma unroll
-          for (int i = 0; i < P; ++i) cw[c] = ccfma(Uq[i * RAM + c], w[i], cw[c]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        z[i] = w[i];
-#pragma unroll
-        for (int c = 0; c < RAM; ++c)
-          if (c < r_a) z[i] = csub(z[i], cmul(Uq[i * RAM + c], cw[c]));
-      }
-    }
-    const bool den_ok = den > ES(1e-12) * ES(prm.bs_norm2);
-    float T;
-    if (prm.stat_mode == 0) {
-      ES num = 0;
-#pragma unroll
-      for (int i = 0; i < P; ++i) num += cabs2(z[i]);
-      T = den_ok ? float(num / den) : 0.f;
-    } else {
-      EC hz = czero<EC>(), fh[P], hs[P];
-#pragma unroll
-      for (int i = 0; i < P; ++i) fh[i] = hs[i] = cto<EC>(prm.h_s[i]);
-#pragma unroll
-      for (int c = 0; c < RAM; ++c) {
-        if (c >= r_a) continue;
-        EC ch = czero<EC>();
-#pragma unroll
-        for (int i = 0; i < P; ++i) ch = ccfma(Uq[i * RAM + c], hs[i], ch);
-#pragma unroll
-        for (int i = 0; i < P; ++i) fh[i] = csub(fh[i], cmul(Uq[i * RAM + c], ch));
-      }
-      ES hfh = 0;
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        hz = ccfma(hs[i], z[i], hz);
-        hfh += hs[i].x * fh[i].x + hs[i].y * fh[i].y;
-      }
-      const bool ok = den_ok && hfh > ES(1e-12) * ES(prm.h_norm2);
-      T = ok ? float(cabs2(hz) / (hfh * den)) : 0.f;
-    }
-    if (!isfinite(T)) T = NAN;
-    if (flag == 1) T = 0.f;
-    if (flag == 2) T = NAN;
-    if (slot_ok && tk == 0) {
-      prm.T[pidx] = T;
-      if (MODE == kModeRun && prm.D) prm.D[pidx] = (T > prm.tau) ? 1 : 0;
-      if (MODE == kModeProbe) {
-        if (prm.eta) prm.eta[pidx] = sQeta[tg];
-        if (prm.iters) prm.iters[pidx] = sQit[tg];
-      }
-    }
-    if (MODE == kModeProbe && slot_ok) {
-      if (prm.UA && tk < P) {
-#pragma unroll
-        for (int c = 0; c < RAM; ++c)
-          if (c < r_a) prm.UA[(pidx * P + tk) * r_a + c] = (flag != 0) ? cz() : tof(sQUA[tg][tk * RAM + c]);
-      }
-      if (prm.UB && tk < Q) {
-#pragma unroll
-        for (int c = 0; c < RBM; ++c)
-          if (c < r_b) prm.UB[(pidx * Q + tk) * r_b + c] = (flag != 0) ? cz() : tof(vb[c]);
-      }
-    }
-    wave_sync();
+    tail_batch<P, Q, RBM, MODE, EC, false>(prm, Bq, tg, nfill, sQflag, sQidx, sQeta, sQit, sQUA, tail_scratch,
+                                           PREC ? 1e-12 : 2e-6);
   };
 
   // Sliding window (run mode, FP32 path): a pixel at column 1..3 of its 4x4
@@ -1480,36 +1519,51 @@ __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restr
 // BF16 hi/lo pairs for PREC 1, FP32 for PREC 0), double-buffered: the global
 // loads of the next chunk are in flight while the waves run the MFMAs of the
 // current one.  S is kept as its upper q x q blocks S(i,j), i <= j (the lower
-// blocks are their conjugate transposes), which halves its LDS footprint.
-// LR-Kron sweeps run over all 256 lanes with the block sums reduced across
-// waves through LDS; the small eigensolves and the statistic are computed
-// identically by every wave.
+// blocks are their conjugate transposes), which halves its LDS footprint, and
+// it outlives the pixel: in run mode a pixel at column 1..3 of its 4 x 4
+// unit row starts from its left neighbour's n*S and stages only the training
+// vectors that enter the stencil (added) and leave it (subtracted), as the
+// narrow FP32 kernels do.  LR-Kron sweeps run over all 256 lanes with the
+// block sums reduced across waves through LDS; the small factor-A solves are
+// computed identically by every wave.  The Hermitian time factors are queued
+// in LDS and the batched tail (a6 + a8) runs 64/q' pixels per wave on all
+// four waves at once.
 // ====================================================================
 template <int P, int Q, int RBM, int PREC>
 struct WideLds {
   using EC = typename Pick<PREC == 1, double2, float2>::type;
   static constexpr int PQ = P * Q;
   static constexpr int NB = (PQ + 15) / 16;
-  static constexpr int QS = Q + 1;                                   // padded block row
   static constexpr int NBLK = P * (P + 1) / 2;
   static constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
-  static constexpr size_t sS = sizeof(float2) * NBLK * Q * QS;       // upper blocks of S
-  // staging (aliases S): per buffer NB*16 rows x 16 vectors
+  static constexpr int G = Groups<Q>::G;
+  static constexpr int NQ = 4 * G;                                   // pixels per batched tail
+  static constexpr size_t kS = sizeof(float2) * NBLK * Q * (Q + 1);  // upper blocks of S
   static constexpr size_t rowb = PREC ? 80 : 144;                    // padded bytes per staged row
   static constexpr size_t stage1 = PREC ? 2 * NB * 16 * rowb : NB * 16 * rowb;   // hi + lo, or fp32
-  static constexpr size_t sStage = 2 * stage1;
+  static constexpr size_t kStage = 2 * stage1;
+  static constexpr size_t kTail = sizeof(EC) * RBM * Q * G * 4;      // subspace scratch of the 4 waves
+  static constexpr size_t kST = kStage > kTail ? kStage : kTail;
   static constexpr size_t oS = 0;
-  static constexpr size_t oRed = ((sS > sStage ? sS : sStage) + 15) / 16 * 16;   // float[4][2*P*P + 8]
-  static constexpr int KRED = 2 * P * P + 8;
-  static constexpr size_t oRedD = oRed + sizeof(float) * 4 * KRED;  // double[4]
-  static constexpr size_t oUA = (oRedD + sizeof(double) * 4 + 15) / 16 * 16;      // EC[P*RAM]
+  static constexpr size_t oStage = (kS + 15) / 16 * 16;              // staging; tail scratch between pixels
+  static constexpr size_t oHq = oStage + (kST + 15) / 16 * 16;       // float2[NQ][Q*Q]: queued Herm(B)
+  static constexpr size_t oQUA = oHq + sizeof(float2) * NQ * Q * Q;  // EC[NQ][P*RAM]: queued U_A
+  static constexpr size_t oUA = oQUA + sizeof(EC) * NQ * P * RAM;    // EC[P*RAM]
   static constexpr size_t oAh = oUA + sizeof(EC) * P * RAM;          // EC[P*P]
-  static constexpr size_t oVa = oAh + sizeof(EC) * P * P;            // EC[P*RAM]
-  static constexpr size_t oA = oVa + sizeof(EC) * P * RAM;           // float2[P*P]
+  static constexpr size_t oRedD = oAh + sizeof(EC) * P * P;          // double[4]
+  static constexpr size_t oQidx = oRedD + sizeof(double) * 4;        // int64[NQ]
+  static constexpr size_t oRed = oQidx + sizeof(int64_t) * NQ;       // float[4][KRED]
+  static constexpr int KRED = 2 * P * P + 8;
+  static constexpr size_t oA = oRed + sizeof(float) * 4 * KRED;      // float2[P*P]
   static constexpr size_t oAp = oA + sizeof(float2) * P * P;         // float2[P*P]: block sums (A_0, R b*)
   static constexpr size_t oB = oAp + sizeof(float2) * P * P;         // float2[Q*Q]: current b
   static constexpr size_t oOff = oB + sizeof(float2) * Q * Q;        // int[kMaxN]
-  static constexpr size_t bytes = (oOff + sizeof(int) * kMaxN + 15) / 16 * 16;
+  static constexpr size_t oDel = oOff + sizeof(int) * kMaxN;         // int[2*kMaxDelta]: entering, leaving
+  static constexpr size_t oQflag = oDel + sizeof(int) * 2 * kMaxDelta;   // int[NQ]
+  static constexpr size_t oQit = oQflag + sizeof(int) * NQ;          // int[NQ]
+  static constexpr size_t oQeta = oQit + sizeof(int) * NQ;           // float[NQ]
+  static constexpr size_t bytes = (oQeta + sizeof(float) * NQ + 15) / 16 * 16;
+  static_assert(bytes <= 160 * 1024, "LDS of one workgroup");
 };
 
 __device__ __forceinline__ void block_sync() { __syncthreads(); }
@@ -1546,43 +1600,49 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
   using L = WideLds<P, Q, RBM, PREC>;
   constexpr int PQ = P * Q;
   constexpr int NB = L::NB;
-  constexpr int QS = L::QS;
+  constexpr int QS = Q + 1;
   constexpr int QQ = Q * Q;
   constexpr int NE = (QQ + 255) / 256;      // q x q entries per lane
   constexpr int RAM = L::RAM;
   constexpr int NPAIR = NB * (NB + 1) / 2;
   constexpr int MYP = (NPAIR + 3) / 4;      // tile pairs per wave (round-robin)
-  constexpr int KRED = L::KRED;
   constexpr int QP = Groups<Q>::QP;
+  constexpr int G = L::G;
+  constexpr int NQ = L::NQ;
 
   float2* const sS = reinterpret_cast<float2*>(lds + L::oS);
-  char* const stage = lds + L::oS;
+  char* const stage = lds + L::oStage;
   float* const red = reinterpret_cast<float*>(lds + L::oRed);
   double* const redd = reinterpret_cast<double*>(lds + L::oRedD);
   EC* const sUA = reinterpret_cast<EC*>(lds + L::oUA);
   EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
-  EC* const sVa = reinterpret_cast<EC*>(lds + L::oVa);
   float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
   float2* const sAp = reinterpret_cast<float2*>(lds + L::oAp);
   float2* const sB = reinterpret_cast<float2*>(lds + L::oB);
   int* const sOff = reinterpret_cast<int*>(lds + L::oOff);
+  int* const sDel = reinterpret_cast<int*>(lds + L::oDel);
+  float2* const sHq = reinterpret_cast<float2*>(lds + L::oHq);
+  EC (*const sQUA)[P * RAM] = reinterpret_cast<EC (*)[P * RAM]>(lds + L::oQUA);
+  int64_t* const sQidx = reinterpret_cast<int64_t*>(lds + L::oQidx);
+  int* const sQflag = reinterpret_cast<int*>(lds + L::oQflag);
+  int* const sQit = reinterpret_cast<int*>(lds + L::oQit);
+  float* const sQeta = reinterpret_cast<float*>(lds + L::oQeta);
 
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  // entries of a q x q block a lane visits in the block passes: e = lane + 64 m,
-  // at row-major (k*QS + l) and transposed (l*QS + k) offsets
-  constexpr int NL = (QQ + 63) / 64;
-  int eo[NL], et[NL];
-#pragma unroll
-  for (int m = 0; m < NL; ++m) {
-    const int e = lane + 64 * m, k = e / Q, l = e - (e / Q) * Q;
-    eo[m] = k * QS + l;
-    et[m] = l * QS + k;
-  }
+  // the wave index is uniform: keep it (and the tile pairs below) in SGPRs
+  const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  constexpr int NL = (QQ + 63) / 64;   // q x q block entries per lane in the block passes
   const int n = prm.n, H = prm.H, W = prm.W;
   const int r_a = prm.r_a, r_b = prm.r_b;
 
+  // sample offsets of the stencil, and of the entering then leaving vectors
+  // of a one-pixel move to the right
+  const int ndel = prm.nadd >= 0 ? prm.nadd + prm.nrem : 0;
   block_sync();
   for (int m = tid; m < n; m += 256) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
+  for (int m = tid; m < ndel; m += 256) {
+    const int16_t* d = (m < prm.nadd) ? prm.dadd + 2 * m : prm.drem + 2 * (m - prm.nadd);
+    sDel[m] = (int(d[0]) * W + int(d[1])) * Q;
+  }
   block_sync();
 
   // this wave's tile pairs (I, J), I <= J, round-robin over the upper tiles
@@ -1603,26 +1663,42 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     for (int u = 0; u < MYP; ++u) pOk[u] = (u * 4 + wave) < NPAIR;
   }
 
-  // staging items of this thread: (vector v, row rho) = divmod(tid + 256 it, PQ)
+  // staging items of this thread: (vector v, row rho) = divmod(tid + 256 it, PQ),
+  // recomputed where used (cheaper than holding them in registers)
   constexpr int NIT = (16 * PQ + 255) / 256;
-  int it_v[NIT], it_rho[NIT], it_off[NIT];
-  bool it_ok[NIT];
-#pragma unroll
-  for (int it = 0; it < NIT; ++it) {
-    const int idx = tid + 256 * it;
-    it_ok[it] = idx < 16 * PQ;
-    const int v = it_ok[it] ? idx / PQ : 0, rho = it_ok[it] ? idx - (idx / PQ) * PQ : 0;
-    it_v[it] = v;
-    it_rho[it] = rho;
-    const int ch = rho / Q, j = rho - (rho / Q) * Q;
-    it_off[it] = ch * H * W * Q + j;
-  }
+  const int64_t plane = int64_t(H) * W * Q;
+  auto item = [&](int it, int* v, int* rho) __attribute__((always_inline)) -> bool {
+    const int e = tid + 256 * it;
+    *v = e / PQ;
+    *rho = e - *v * PQ;
+    return e < 16 * PQ;
+  };
 
-  for (int64_t itp = 0; itp < count; ++itp) {
+  // ------------------------------------------ a6 + a8 for the queued pixels
+  // wave w serves queue slots w*G .. w*G + G - 1; lane k of a slot's group
+  // takes row k of its Hermitian time factor (column k, conjugated: the
+  // stored factor is exactly Hermitian)
+  auto tail = [&](int nfill) __attribute__((always_inline)) {
+    const int slot = wave * G + lane / QP, tk = lane % QP;
+    const bool own = slot < nfill && tk < Q;
+    float2 Bq[Q];
+#pragma unroll
+    for (int l = 0; l < Q; ++l) Bq[l] = own ? cconj(sHq[(slot < nfill ? slot : 0) * QQ + l * Q + tk]) : cz();
+    tail_batch<P, Q, RBM, MODE, EC, true>(prm, Bq, slot, nfill, sQflag, sQidx, sQeta, sQit, sQUA,
+                                          reinterpret_cast<EC*>(stage) + wave * (RBM * Q * G),
+                                          PREC ? 1e-12 : 2e-6);
+    block_sync();
+  };
+
+  int nq = 0;
+  bool chain = false;   // the previous position left a usable S in LDS
+  auto pixel = [&](int64_t itp) __attribute__((always_inline)) {
     int64_t idx;
     int r, c;
+    const bool left_ok = chain;
+    chain = false;
     if (MODE == kModeRun) {
-      if (!tiled_pixel(first + itp, H, W, &r, &c)) continue;
+      if (!tiled_pixel(first + itp, H, W, &r, &c)) return;
       idx = int64_t(r) * W + c;
     } else {
       idx = first + itp;
@@ -1645,42 +1721,69 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         if (prm.UB)
           for (int e = tid; e < Q * r_b; e += 256) prm.UB[idx * Q * r_b + e] = cz();
       }
-      continue;
+      return;
     }
     const float2* xp = prm.x + (int64_t(r) * W + c) * Q;
 
     // ------------------------------------------------------------ a2 SCM
+    // Full sum over the n stencil vectors, or (sliding window) the left
+    // neighbour's n*S plus the entering vectors minus the leaving ones:
+    // list entries m < npos are added, the others subtracted.
+    const bool slide = MODE == kModeRun && left_ok && ((first + itp) & 3) != 0 && prm.nadd >= 0;
+    const int* const list = slide ? sDel : sOff;
+    const int cnt = slide ? ndel : n;
+    const int npos = slide ? prm.nadd : n;
+    const float fn = float(n);
+    const int trow = 4 * (lane >> 4), tcol = lane & 15;
     f4 accR[MYP], accI[MYP];
 #pragma unroll
-    for (int u = 0; u < MYP; ++u) accR[u] = accI[u] = f4{0.f, 0.f, 0.f, 0.f};
-    const int nch = (n + 15) >> 4;
+    for (int u = 0; u < MYP; ++u) {
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        // element (a, b) of the old S, read from its upper block (conjugated
+        // when it lies below the block diagonal), without branches
+        const int a = 16 * pI[u] + trow + q4, b = 16 * pJ[u] + tcol;
+        const int ba = a / Q, bb = b / Q, ka = a - ba * Q, kb = b - bb * Q;
+        const bool upper = ba <= bb;
+        const int off = upper ? sblk<P, Q>(ba, bb) + ka * QS + kb : sblk<P, Q>(bb, ba) + kb * QS + ka;
+        const bool use = slide && pOk[u] && a < PQ && b < PQ;
+        const float2 v = sS[use ? off : 0];
+        accR[u][q4] = use ? v.x * fn : 0.f;
+        accI[u][q4] = use ? (upper ? v.y : -v.y) * fn : 0.f;
+      }
+    }
+    const int nch = (cnt + 15) >> 4;
     float2 pre[NIT];
     auto gload = [&](int ch) __attribute__((always_inline)) {
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
-        const int m = ch * 16 + it_v[it];
-        const bool ok = it_ok[it] && m < n;
-        pre[it] = load_or_zero(xp + it_off[it] + sOff[ok ? m : 0], ok);
+        int v, rho;
+        const bool in = item(it, &v, &rho);
+        const int m = ch * 16 + v;
+        const bool ok = in && m < cnt;
+        const int chn = rho / Q;
+        pre[it] = load_or_zero(xp + chn * plane + (rho - chn * Q) + list[ok ? m : 0], ok);
       }
     };
     auto sstore = [&](int buf) __attribute__((always_inline)) {
       char* base = stage + buf * L::stage1;
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
-        if (!it_ok[it]) continue;
+        int v, rho;
+        if (!item(it, &v, &rho)) continue;
         if constexpr (PREC == 1) {
           const float a = pre[it].x, b = pre[it].y;
           const __bf16 ha = (__bf16)a, hb = (__bf16)b;
           const __bf16 la = (__bf16)(a - (float)ha), lb = (__bf16)(b - (float)hb);
-          __bf16* hrow = reinterpret_cast<__bf16*>(base + size_t(it_rho[it]) * L::rowb);
-          __bf16* lrow = reinterpret_cast<__bf16*>(base + size_t(NB * 16 + it_rho[it]) * L::rowb);
-          hrow[2 * it_v[it]] = ha;
-          hrow[2 * it_v[it] + 1] = hb;
-          lrow[2 * it_v[it]] = la;
-          lrow[2 * it_v[it] + 1] = lb;
+          __bf16* hrow = reinterpret_cast<__bf16*>(base + size_t(rho) * L::rowb);
+          __bf16* lrow = reinterpret_cast<__bf16*>(base + size_t(NB * 16 + rho) * L::rowb);
+          hrow[2 * v] = ha;
+          hrow[2 * v + 1] = hb;
+          lrow[2 * v] = la;
+          lrow[2 * v + 1] = lb;
         } else {
-          float2* row = reinterpret_cast<float2*>(base + size_t(it_rho[it]) * L::rowb);
-          row[it_v[it]] = pre[it];
+          float2* row = reinterpret_cast<float2*>(base + size_t(rho) * L::rowb);
+          row[v] = pre[it];
         }
       }
     };
@@ -1693,17 +1796,23 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       const char* base = stage + buf * L::stage1;
       const int g = lane >> 4, rr = lane & 15;
       if constexpr (PREC == 1) {
-        // operand of block I: row 16 I + rr, vectors 4g..4g+3 (re, im) = 16 bytes
-        auto ld = [&](int I, bool lo) __attribute__((always_inline)) -> bf8 {
+        // operand of block I: row 16 I + rr, vectors 4g..4g+3 (re, im) = 16 bytes;
+        // the row operand of a subtracted vector is negated (sign bits of its pair)
+        u4 msk;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) msk[e] = (ch * 16 + 4 * g + e >= npos) ? 0x80008000u : 0u;
+        auto ld = [&](int I, bool lo) __attribute__((always_inline)) -> u4 {
           const int row = 16 * I + rr;
-          if (row >= PQ) return __builtin_bit_cast(bf8, u4{0u, 0u, 0u, 0u});
+          if (row >= PQ) return u4{0u, 0u, 0u, 0u};
           const char* p = base + size_t((lo ? NB * 16 : 0) + row) * L::rowb + g * 16;
-          return __builtin_bit_cast(bf8, *reinterpret_cast<const u4*>(p));
+          return *reinterpret_cast<const u4*>(p);
         };
 #pragma unroll
         for (int u = 0; u < MYP; ++u) {
           if (!pOk[u]) continue;
-          const bf8 hI = ld(pI[u], false), lI = ld(pI[u], true), hJ = ld(pJ[u], false), lJ = ld(pJ[u], true);
+          const bf8 hI = __builtin_bit_cast(bf8, ld(pI[u], false) ^ msk);
+          const bf8 lI = __builtin_bit_cast(bf8, ld(pI[u], true) ^ msk);
+          const bf8 hJ = __builtin_bit_cast(bf8, ld(pJ[u], false)), lJ = __builtin_bit_cast(bf8, ld(pJ[u], true));
           const bf8 zh = swap_neg(hI), zl = swap_neg(lI);
           accR[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(hI, hJ, accR[u], 0, 0, 0);
           accI[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, hJ, accI[u], 0, 0, 0);
@@ -1716,6 +1825,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         // 4 K-steps of 4 vectors: lane (row rr, vector 4 s + g)
 #pragma unroll
         for (int s4 = 0; s4 < 4; ++s4) {
+          const float sg = (ch * 16 + 4 * s4 + g >= npos) ? -1.f : 1.f;
           auto ld = [&](int I) __attribute__((always_inline)) -> float2 {
             const int row = 16 * I + rr;
             if (row >= PQ) return cz();
@@ -1724,7 +1834,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
           for (int u = 0; u < MYP; ++u) {
             if (!pOk[u]) continue;
-            const float2 a = ld(pI[u]), b = ld(pJ[u]);
+            const float2 a = cscale(ld(pI[u]), sg), b = ld(pJ[u]);
             accR[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, accR[u], 0, 0, 0);
             accI[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, accI[u], 0, 0, 0);
             accR[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, accR[u], 0, 0, 0);
@@ -1735,21 +1845,18 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       if (ch + 1 < nch) sstore(buf ^ 1);
       block_sync();
     }
-    // S to LDS as upper blocks (the staging area is dead after the barrier above)
+    // S to LDS as upper blocks: every element (a, b), a <= b, has one writer
+    // (the staging barrier above also ends every wave's reload of the old S)
+    block_sync();
     {
-      const float inv_n = 1.f / float(n);
-      const int trow = 4 * (lane >> 4), tcol = lane & 15;
+      const float inv_n = 1.f / fn;
 #pragma unroll
       for (int u = 0; u < MYP; ++u) {
         if (!pOk[u]) continue;
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int a = 16 * pI[u] + trow + q4, b = 16 * pJ[u] + tcol;
-          if (a >= PQ || b >= PQ) continue;
-          const float2 v = make_float2(accR[u][q4] * inv_n, accI[u][q4] * inv_n);
-          const int ba = a / Q, bb = b / Q, ka = a - ba * Q, kb = b - bb * Q;
-          if (ba <= bb) sS[((ba * P - ba * (ba - 1) / 2 + (bb - ba)) * Q + ka) * QS + kb] = v;
-          if (bb <= ba) sS[((bb * P - bb * (bb - 1) / 2 + (ba - bb)) * Q + kb) * QS + ka] = cconj(v);
+          if (a < PQ && b < PQ && a <= b) sput<P, Q>(sS, a, b, make_float2(accR[u][q4] * inv_n, accI[u][q4] * inv_n));
         }
       }
     }
@@ -1779,7 +1886,8 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
           if (lane + 64 * m < QQ) {
-            float2 sv = sS[base + (up ? eo[m] : et[m])];
+            const int e = lane + 64 * m, k = e / Q, l = e - k * Q;
+            float2 sv = sS[base + (up ? k * QS + l : l * QS + k)];
             sv.y = up ? sv.y : -sv.y;
             acc = ccfma(wv[m], sv, acc);
             n2 += cabs2(sv);
@@ -1988,116 +2096,39 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
       for (int i = 0; i < P; ++i) sUA[i * RAM] = ua[i];
     }
-    // raw B to LDS (S is dead)
+    chain = !bad;   // this S may seed the right neighbour's
+    block_sync();
+    // ------------------------------------------ enqueue for the batched tail
+    // (sB holds the final b = R^T conj(a) / ||a||^2 of a finite pixel)
+    float2* const hq = sHq + nq * QQ;
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = tid + 256 * t;
-      if (e < QQ) sS[e] = bv[t];
-    }
-    block_sync();
-    // ---------------------------------------------- a6 + a8, every wave alike
-    const bool rok = lane < Q;
-    float2 Bq[Q];
-#pragma unroll
-    for (int l = 0; l < Q; ++l)
-      Bq[l] = rok ? cscale(cadd(sS[lane * Q + l], cconj(sS[l * Q + lane])), 0.5f) : cz();
-    block_sync();
-    const bool use = rok && !zero && !bad;
-    EC vb[RBM];
-#pragma unroll
-    for (int cc = 0; cc < RBM; ++cc) vb[cc] = czero<EC>();
-    if (r_b > 0)
-      group_subspace<RBM, QP, Q, EC>(Bq, use, r_b, vb, reinterpret_cast<EC*>(sS) + QQ, true, 200,
-                                     PREC ? 1e-12 : 2e-6);
-    const EC bsk = use ? cto<EC>(prm.b_s[lane]) : czero<EC>();
-    EC gk = bsk;
-    if (r_b > 0) {
-#pragma unroll
-      for (int cc = 0; cc < RBM; ++cc) {
-        if (cc >= r_b) continue;
-        const EC coef = gsum<QP>(ccfma(vb[cc], bsk, czero<EC>()));
-        if (use) gk = csub(gk, cmul(vb[cc], coef));
+      if (e < QQ) {
+        const int k = e / Q, l = e - (e / Q) * Q;
+        hq[e] = cscale(cadd(sB[k * Q + l], cconj(sB[l * Q + k])), 0.5f);
       }
     }
-    EC w[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const EC xv = use ? cto<EC>(xp[int64_t(i) * H * W * Q + lane]) : czero<EC>();
-      w[i] = gsum<QP>(cmul(xv, cconj(gk)));
-    }
-    const ES den = gsum<QP>(ES(bsk.x * gk.x + bsk.y * gk.y));
-    EC z[P];
-    {
-      EC cw[RAM];
-#pragma unroll
-      for (int cc = 0; cc < RAM; ++cc) {
-        cw[cc] = czero<EC>();
-        if (cc < r_a) {
-#pragma unroll
-          for (int i = 0; i < P; ++i) cw[cc] = ccfma(sUA[i * RAM + cc], w[i], cw[cc]);
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        z[i] = w[i];
-#pragma unroll
-        for (int cc = 0; cc < RAM; ++cc)
-          if (cc < r_a) z[i] = csub(z[i], cmul(sUA[i * RAM + cc], cw[cc]));
-      }
-    }
-    const bool den_ok = den > ES(1e-12) * ES(prm.bs_norm2);
-    float T;
-    if (prm.stat_mode == 0) {
-      ES num = 0;
-#pragma unroll
-      for (int i = 0; i < P; ++i) num += cabs2(z[i]);
-      T = den_ok ? float(num / den) : 0.f;
-    } else {
-      EC hz = czero<EC>(), fh[P], hs[P];
-#pragma unroll
-      for (int i = 0; i < P; ++i) fh[i] = hs[i] = cto<EC>(prm.h_s[i]);
-#pragma unroll
-      for (int cc = 0; cc < RAM; ++cc) {
-        if (cc >= r_a) continue;
-        EC chh = czero<EC>();
-#pragma unroll
-        for (int i = 0; i < P; ++i) chh = ccfma(sUA[i * RAM + cc], hs[i], chh);
-#pragma unroll
-        for (int i = 0; i < P; ++i) fh[i] = csub(fh[i], cmul(sUA[i * RAM + cc], chh));
-      }
-      ES hfh = 0;
-#pragma unroll
-      for (int i = 0; i < P; ++i) {
-        hz = ccfma(hs[i], z[i], hz);
-        hfh += hs[i].x * fh[i].x + hs[i].y * fh[i].y;
-      }
-      const bool ok = den_ok && hfh > ES(1e-12) * ES(prm.h_norm2);
-      T = ok ? float(cabs2(hz) / (hfh * den)) : 0.f;
-    }
-    if (!isfinite(T)) T = NAN;
-    if (zero) T = 0.f;
-    if (bad) T = NAN;
     if (tid == 0) {
-      prm.T[idx] = T;
-      if (MODE == kModeRun && prm.D) prm.D[idx] = (T > prm.tau) ? 1 : 0;
-      if (MODE == kModeProbe) {
-        if (prm.eta) prm.eta[idx] = eta;
-        if (prm.iters) prm.iters[idx] = iters;
-      }
+      sQidx[nq] = idx;
+      sQflag[nq] = bad ? 2 : (zero ? 1 : 0);
+      sQeta[nq] = eta;
+      sQit[nq] = iters;
     }
-    if (MODE == kModeProbe && wave == 0) {
-      if (prm.UA && lane < P) {
-#pragma unroll
-        for (int cc = 0; cc < RAM; ++cc)
-          if (cc < r_a) prm.UA[(idx * P + lane) * r_a + cc] = (zero || bad) ? cz() : tof(sUA[lane * RAM + cc]);
-      }
-      if (prm.UB && lane < Q) {
-#pragma unroll
-        for (int cc = 0; cc < RBM; ++cc)
-          if (cc < r_b) prm.UB[(idx * Q + lane) * r_b + cc] = (zero || bad) ? cz() : tof(vb[cc]);
-      }
-    }
+    if (tid < P * RAM) sQUA[nq][tid] = (zero || bad) ? czero<EC>() : sUA[tid];
     block_sync();
+    ++nq;
+  };
+
+  // one call site each for the pixel body and the tail
+  for (int64_t itp = 0;; ++itp) {
+    const bool more = itp < count;
+    if (more) pixel(itp);
+    if (nq == NQ || (!more && nq > 0)) {
+      tail(nq);
+      nq = 0;
+    }
+    if (!more) break;
   }
 }
 

@@ -340,6 +340,9 @@ def test_wide_pixel_parity(case):
     dB = np.abs(UB @ np.conj(np.swapaxes(UB, 1, 2)) - out["U_B"][sel] @ np.conj(np.swapaxes(out["U_B"][sel], 1, 2))).max()
     UA = pr["U_A"].cpu().numpy().astype(np.complex128)
     dA = np.abs(UA @ np.conj(np.swapaxes(UA, 1, 2)) - out["U_A"][sel] @ np.conj(np.swapaxes(out["U_A"][sel], 1, 2))).max()
-    np.testing.assert_array_equal(pr["T"].cpu().numpy(), Tg[pix[:, 0], pix[:, 1]])
-    note(f"[wide {case}] probe projector distance A {dA:.2e} B {dB:.2e}")
+    # the frame pass updates most covariances from the left neighbour's, the
+    # probe sums every pixel's from scratch: they differ by summation order
+    eP = rel_err(pr["T"].cpu().numpy(), Tg[pix[:, 0], pix[:, 1]]).max()
+    note(f"[wide {case}] probe projector distance A {dA:.2e} B {dB:.2e}, probe vs frame T {eP:.2e}")
+    assert eP <= 2e-5
     assert dA <= 1e-4 and dB <= 1e-4
