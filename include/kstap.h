@@ -160,7 +160,7 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
  *
  * stap_batch_create validates every tile, uploads a tile table to device
  * memory it owns, numbers the work items (runs of `pix_per_item` consecutive
- * positions of one tile's tiled pixel order, rounded up to a multiple of 4)
+ * positions of one tile's tiled pixel order, rounded up to a multiple of 16)
  * longest tile first within each kernel class, and
  * builds one HIP graph: a counter-reset kernel node followed, as parallel
  * branches, by one persistent kernel node per kernel class present; every

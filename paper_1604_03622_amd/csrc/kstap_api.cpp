@@ -351,23 +351,33 @@ stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out) {
     pl->dc_max = std::max(pl->dc_max, pl->stencil[2 * m + 1]);
   }
   {
-    // one-pixel move to the right: o enters if o is in the stencil and
-    // o + (0, 1) is not; o leaves if o + (0, 1) is in the stencil and o is not
+    // one-pixel moves right, left and down (kstap::Move): the previous pixel's
+    // stencil, seen from the new pixel, is the stencil shifted by -d; o enters
+    // if o is in the stencil and o + d is not, o - d leaves if o is in the
+    // stencil and o - d is not
     std::set<std::pair<int, int>> st;
     for (int m = 0; m < c.n; ++m) st.insert({pl->stencil[2 * m], pl->stencil[2 * m + 1]});
-    for (const auto& o : st) {
-      if (!st.count({o.first, o.second + 1})) {
-        pl->dadd.push_back(o.first);
-        pl->dadd.push_back(o.second);
+    const int mvd[3][2] = {{0, 1}, {0, -1}, {1, 0}};
+    bool fits = true;
+    for (int mv = 0; mv < 3; ++mv) {
+      for (const auto& o : st) {
+        if (!st.count({o.first + mvd[mv][0], o.second + mvd[mv][1]})) {
+          pl->dadd[mv].push_back(o.first);
+          pl->dadd[mv].push_back(o.second);
+        }
+        if (!st.count({o.first - mvd[mv][0], o.second - mvd[mv][1]})) {
+          pl->drem[mv].push_back(o.first - mvd[mv][0]);
+          pl->drem[mv].push_back(o.second - mvd[mv][1]);
+        }
       }
-      if (!st.count({o.first, o.second - 1})) {
-        pl->drem.push_back(o.first);
-        pl->drem.push_back(o.second - 1);
-      }
+      fits = fits && pl->dadd[mv].size() <= 2 * size_t(kstap::kMaxDelta) &&
+             pl->drem[mv].size() <= 2 * size_t(kstap::kMaxDelta);
     }
-    if (pl->dadd.size() > 2 * size_t(kstap::kMaxDelta) || pl->drem.size() > 2 * size_t(kstap::kMaxDelta)) {
-      pl->dadd.clear();
-      pl->drem.clear();
+    if (!fits) {
+      for (int mv = 0; mv < 3; ++mv) {
+        pl->dadd[mv].clear();
+        pl->drem[mv].clear();
+      }
     }
   }
   pl->b_steer.assign(2 * c.q, 0.f);
@@ -451,11 +461,9 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
   k.T = T;
   k.D = D;
   const int64_t total = kstap::tiled_positions(H, W);
-  // enough workgroups to cover 256 CUs several times over, 4 to 16 positions
-  // each (a multiple of 4: runs start on a unit row, see the sliding window)
-  int64_t ppb = total / (256 * 8 * 4);
-  ppb = std::max<int64_t>(4, std::min<int64_t>(16, ppb));
-  ppb = (ppb + 3) / 4 * 4;
+  // one 4 x 4 unit per workgroup: runs start on a unit, so the sliding-window
+  // chain (which restarts on every unit) is the same for every decomposition
+  const int64_t ppb = kstap::kUnit * kstap::kUnit;
   k.pix_per_block = int32_t(ppb);
   k.nlogical = int32_t((total + ppb - 1) / ppb);
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -578,7 +586,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
   b->ppb = 16;
   b->grid_mult = 1;
   if (pix_per_item > 0) {
-    b->ppb = (pix_per_item + 3) / 4 * 4;   // runs start on a unit row
+    b->ppb = (pix_per_item + 15) / 16 * 16;   // runs start on a unit
   } else {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(b->signature);
@@ -644,7 +652,7 @@ stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best
     hipEventDestroy(e0);
     return fail(STAP_ERR_DEVICE, "event create failed");
   }
-  const int ppbs[] = {4, 8, 16, 32};
+  const int ppbs[] = {16, 32, 64};
   const int mults[] = {1, 2};
   double best = 1e300;
   int bp = batch->ppb, bm = batch->grid_mult;

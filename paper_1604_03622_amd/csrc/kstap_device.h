@@ -641,7 +641,7 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
     wave_sync();
 }
 
-// Sliding-window update of S (FP32): from the left neighbour's S (in LDS),
+// Sliding-window update of S (FP32): from the previous pixel's S (in LDS),
 // n S += sum over entering vectors x x^H - sum over leaving ones.  sAdd /
 // sRem: byte offsets (kOut past nadd / nrem and for 8 entries beyond).
 // Diagonal tiles take both Im products here (no transpose through LDS), so
@@ -1048,8 +1048,8 @@ struct Lds {
   static constexpr size_t oA = oS + sizeof(float2) * (P * (P + 1) / 2) * Q * (Q + 1);   // float2[P*P]
   static constexpr size_t oQidx = oA + sizeof(float2) * P * P;            // int64[G]
   static constexpr size_t oOff = oQidx + sizeof(int64_t) * G;             // uint32[kMaxN + kOffPad]
-  static constexpr size_t oDelta = oOff + sizeof(uint32_t) * (kMaxN + kOffPad);   // uint32[2][kMaxDelta + 8]
-  static constexpr size_t oQflag = oDelta + sizeof(uint32_t) * 2 * (kMaxDelta + 8);   // int[G]
+  static constexpr size_t oDelta = oOff + sizeof(uint32_t) * (kMaxN + kOffPad);   // uint32[3][2][kMaxDelta + 8] (FP32)
+  static constexpr size_t oQflag = oDelta + (PREC ? 0 : sizeof(uint32_t) * 6 * (kMaxDelta + 8));   // int[G]
   static constexpr size_t oQit = oQflag + sizeof(int) * G;                // int[G]
   static constexpr size_t oQeta = oQit + sizeof(int) * G;                 // float[G]
   static constexpr size_t bytes = ((oQeta + sizeof(float) * G) + 15) / 16 * 16;
@@ -1074,8 +1074,9 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   float2* const sS = reinterpret_cast<float2*>(lds + L::oS);     // S, upper blocks
   float2* const sBT = reinterpret_cast<float2*>(lds + L::oBT);   // raw B, then tail scratch
   uint32_t* const sOffB = reinterpret_cast<uint32_t*>(lds + L::oOff);
-  uint32_t* const sAdd = reinterpret_cast<uint32_t*>(lds + L::oDelta);   // sliding window: entering
-  uint32_t* const sRem = sAdd + kMaxDelta + 8;                            //   and leaving vectors
+  // sliding window: per move, the entering then the leaving vectors
+  uint32_t* const sDelta = reinterpret_cast<uint32_t*>(lds + L::oDelta);
+  constexpr int KD = kMaxDelta + 8;
   float2* const sA = reinterpret_cast<float2*>(lds + L::oA);
   EC* const sUA = reinterpret_cast<EC*>(lds + L::oUA);
   EC* const sAh = reinterpret_cast<EC*>(lds + L::oAh);
@@ -1098,11 +1099,16 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   for (int m = lane; m < kMaxN + kOffPad; m += 64)
     sOffB[m] = (m < n) ? uint32_t(((int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q - prm.st_min) * kSample)
                        : kOut;
-  for (int m = lane; m < kMaxDelta + 8; m += 64) {
-    sAdd[m] = (m < prm.nadd) ? uint32_t(((int(prm.dadd[2 * m]) * W + int(prm.dadd[2 * m + 1])) * Q - prm.st_min) * kSample)
-                             : kOut;
-    sRem[m] = (m < prm.nrem) ? uint32_t(((int(prm.drem[2 * m]) * W + int(prm.drem[2 * m + 1])) * Q - prm.st_min) * kSample)
-                             : kOut;
+  for (int m = lane; m < (PREC ? 0 : 6 * KD); m += 64) {
+    const int t = m / KD, e = m - t * KD, mv = t >> 1;
+    const int cnt = (t & 1) ? prm.nrem[mv] : prm.nadd[mv];
+    uint32_t off = kOut;
+    if (e < cnt) {   // cnt <= kMaxDelta
+      const int dr = (t & 1) ? prm.drem[mv][2 * e] : prm.dadd[mv][2 * e];
+      const int dc = (t & 1) ? prm.drem[mv][2 * e + 1] : prm.dadd[mv][2 * e + 1];
+      off = uint32_t(((dr * W + dc) * Q - prm.st_min) * kSample);
+    }
+    sDelta[m] = off;
   }
   wave_sync();
 
@@ -1132,10 +1138,12 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
                                            PREC ? 1e-12 : 2e-6);
   };
 
-  // Sliding window (run mode, FP32 path): a pixel at column 1..3 of its 4x4
-  // unit row updates its left neighbour's S when this workgroup has just
-  // computed it from finite data; columns 0 start from the full sum.  Runs
-  // start on a unit row, so the choice is the same for every decomposition.
+  // Sliding window (run mode, FP32 path): every position of a 4 x 4 unit but
+  // the first is a one-pixel move from the one before it (the snake of the
+  // tiled order); such a pixel updates the previous pixel's S when this
+  // workgroup has just computed it from finite data.  A unit's first pixel
+  // takes the full sum, and runs start on a unit, so the choice is the same
+  // for every decomposition.
   bool chain = false;
   for (int64_t it = 0; it < count; ++it) {
     int64_t idx;
@@ -1174,10 +1182,12 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     // ---------------------------------------------------------------- a2 SCM
     // (the mixed path is bound by its FP64 solves, not by the cheaper BF16
     // MFMAs, so it always takes the full sum)
-    const bool slide = PREC == 0 && MODE == kModeRun && left_ok && ((first + it) & 3) != 0 && prm.nadd >= 0;
+    const int mv = tiled_move(first + it);
+    const bool slide = PREC == 0 && MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
     if constexpr (PREC == 0) {
       if (slide)
-        scm_fp32_delta<P, Q>(prm.x + win, plane, prm.rec_bytes, sAdd, prm.nadd, sRem, prm.nrem, loff, n, sS);
+        scm_fp32_delta<P, Q>(prm.x + win, plane, prm.rec_bytes, sDelta + 2 * mv * KD, prm.nadd[mv],
+                             sDelta + (2 * mv + 1) * KD, prm.nrem[mv], loff, n, sS);
       else
         scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS, reinterpret_cast<float*>(sBT));
     } else {
@@ -1215,16 +1225,19 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
         a0[e] = cscale(wsum(a0[e]), 1.f / float(QQ));
         an += cabs2(a0[e]);
       }
-      const bool fallback = double(an) <= 1e-24 * normR2;
 #pragma unroll
-      for (int e = 0; e < P * P; ++e) A[e] = fallback ? wsum(pt[e]) : a0[e];
+      for (int e = 0; e < P * P; ++e) A[e] = a0[e];
+      if (double(an) <= 1e-24 * normR2) {   // fallback: partial trace R vec(I_q) (uniform branch)
+#pragma unroll
+        for (int e = 0; e < P * P; ++e) A[e] = wsum(pt[e]);
+      }
     }
 
     float eta = 0.f;
     int iters = 0;
     const bool zero = !(normR2 > 0.0);
     const bool bad = !isfinite(normR2);
-    chain = !bad;   // this S may seed the right neighbour's
+    chain = !bad;   // this S may seed the next pixel's
     float2 bv[NE];
 #pragma unroll
     for (int t = 0; t < NE; ++t) bv[t] = cz();
@@ -1520,10 +1533,10 @@ __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restr
 // loads of the next chunk are in flight while the waves run the MFMAs of the
 // current one.  S is kept as its upper q x q blocks S(i,j), i <= j (the lower
 // blocks are their conjugate transposes), which halves its LDS footprint, and
-// it outlives the pixel: in run mode a pixel at column 1..3 of its 4 x 4
-// unit row starts from its left neighbour's n*S and stages only the training
-// vectors that enter the stencil (added) and leave it (subtracted), as the
-// narrow FP32 kernels do.  LR-Kron sweeps run over all 256 lanes with the
+// it outlives the pixel: in run mode every pixel of a 4 x 4 unit but the
+// first starts from the previous pixel's n*S (a one-pixel move along the
+// unit's snake) and stages only the training vectors that enter the stencil
+// (added) and leave it (subtracted), as the narrow FP32 kernels do.  LR-Kron sweeps run over all 256 lanes with the
 // block sums reduced across waves through LDS; the small factor-A solves are
 // computed identically by every wave.  The Hermitian time factors are queued
 // in LDS and the batched tail (a6 + a8) runs 64/q' pixels per wave on all
@@ -1558,8 +1571,8 @@ struct WideLds {
   static constexpr size_t oAp = oA + sizeof(float2) * P * P;         // float2[P*P]: block sums (A_0, R b*)
   static constexpr size_t oB = oAp + sizeof(float2) * P * P;         // float2[Q*Q]: current b
   static constexpr size_t oOff = oB + sizeof(float2) * Q * Q;        // int[kMaxN]
-  static constexpr size_t oDel = oOff + sizeof(int) * kMaxN;         // int[2*kMaxDelta]: entering, leaving
-  static constexpr size_t oQflag = oDel + sizeof(int) * 2 * kMaxDelta;   // int[NQ]
+  static constexpr size_t oDel = oOff + sizeof(int) * kMaxN;         // int[3][2*kMaxDelta]: per move, entering, leaving
+  static constexpr size_t oQflag = oDel + sizeof(int) * 6 * kMaxDelta;   // int[NQ]
   static constexpr size_t oQit = oQflag + sizeof(int) * NQ;          // int[NQ]
   static constexpr size_t oQeta = oQit + sizeof(int) * NQ;           // float[NQ]
   static constexpr size_t bytes = (oQeta + sizeof(float) * NQ + 15) / 16 * 16;
@@ -1568,21 +1581,7 @@ struct WideLds {
 
 __device__ __forceinline__ void block_sync() { __syncthreads(); }
 
-// Sums K values over the 256 lanes of the workgroup (every lane gets the sum).
-template <int K>
-__device__ __forceinline__ void block_sum(float (&v)[K], float* red) {
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = wsum(v[k]);
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) red[w * K + k] = v[k];
-  }
-  block_sync();
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = (red[k] + red[K + k]) + (red[2 * K + k] + red[3 * K + k]);
-  block_sync();
-}
+// Sums a double over the 256 lanes of the workgroup (every lane gets the sum).
 __device__ __forceinline__ double block_sumd(double v, double* red) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   v = wsumd(v);
@@ -1634,14 +1633,19 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
   const int n = prm.n, H = prm.H, W = prm.W;
   const int r_a = prm.r_a, r_b = prm.r_b;
 
-  // sample offsets of the stencil, and of the entering then leaving vectors
-  // of a one-pixel move to the right
-  const int ndel = prm.nadd >= 0 ? prm.nadd + prm.nrem : 0;
+  // sample offsets of the stencil, and per one-pixel move those of the
+  // entering then the leaving vectors
   block_sync();
   for (int m = tid; m < n; m += 256) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
-  for (int m = tid; m < ndel; m += 256) {
-    const int16_t* d = (m < prm.nadd) ? prm.dadd + 2 * m : prm.drem + 2 * (m - prm.nadd);
-    sDel[m] = (int(d[0]) * W + int(d[1])) * Q;
+  for (int m = tid; m < 6 * kMaxDelta; m += 256) {
+    const int mv = m / (2 * kMaxDelta), e = m - mv * (2 * kMaxDelta);
+    int off = 0;
+    if (prm.nadd[0] >= 0) {
+      const int na = prm.nadd[mv], nr = prm.nrem[mv];   // each <= kMaxDelta
+      if (e < na) off = (int(prm.dadd[mv][2 * e]) * W + int(prm.dadd[mv][2 * e + 1])) * Q;
+      else if (e < na + nr) off = (int(prm.drem[mv][2 * (e - na)]) * W + int(prm.drem[mv][2 * (e - na) + 1])) * Q;
+    }
+    sDel[m] = off;
   }
   block_sync();
 
@@ -1726,13 +1730,15 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     const float2* xp = prm.x + (int64_t(r) * W + c) * Q;
 
     // ------------------------------------------------------------ a2 SCM
-    // Full sum over the n stencil vectors, or (sliding window) the left
-    // neighbour's n*S plus the entering vectors minus the leaving ones:
-    // list entries m < npos are added, the others subtracted.
-    const bool slide = MODE == kModeRun && left_ok && ((first + itp) & 3) != 0 && prm.nadd >= 0;
-    const int* const list = slide ? sDel : sOff;
-    const int cnt = slide ? ndel : n;
-    const int npos = slide ? prm.nadd : n;
+    // Full sum over the n stencil vectors, or (sliding window, a one-pixel
+    // move inside a unit) the previous pixel's n*S plus the entering vectors
+    // minus the leaving ones: list entries m < npos are added, the others
+    // subtracted.
+    const int mv = tiled_move(first + itp);
+    const bool slide = MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
+    const int* const list = slide ? sDel + mv * 2 * kMaxDelta : sOff;
+    const int cnt = slide ? prm.nadd[mv] + prm.nrem[mv] : n;
+    const int npos = slide ? prm.nadd[mv] : n;
     const float fn = float(n);
     const int trow = 4 * (lane >> 4), tcol = lane & 15;
     f4 accR[MYP], accI[MYP];
@@ -1978,13 +1984,21 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
             bv[t] = cz();
           }
         }
-        float bsum[1] = {bb};
-        block_sum<1>(bsum, red);   // its barriers also publish sB
-        if (res) resid = block_sumd(rr, redd);
+        // both sums through one barrier (which also publishes sB); red and
+        // redd are next written after the barrier that ends this sweep
+        bb = wsum(bb);
+        if (res) rr = wsumd(rr);
+        if (lane == 0) {
+          red[wave] = bb;
+          redd[wave] = rr;
+        }
+        block_sync();
+        const float bsum = (red[0] + red[1]) + (red[2] + red[3]);
+        if (res) resid = (redd[0] + redd[1]) + (redd[2] + redd[3]);
         float2 wv[NL];
 #pragma unroll
         for (int m = 0; m < NL; ++m) wv[m] = (lane + 64 * m < QQ) ? sB[lane + 64 * m] : cz();
-        block_pass(wv, 1.f / bsum[0], sAp, nullptr);
+        block_pass(wv, 1.f / bsum, sAp, nullptr);
         block_sync();
       };
       // EIG_{r_a} of Herm(A'), A' = sAp
@@ -2096,7 +2110,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
       for (int i = 0; i < P; ++i) sUA[i * RAM] = ua[i];
     }
-    chain = !bad;   // this S may seed the right neighbour's
+    chain = !bad;   // this S may seed the next pixel's
     block_sync();
     // ------------------------------------------ enqueue for the batched tail
     // (sB holds the final b = R^T conj(a) / ||a||^2 of a finite pixel)

@@ -112,11 +112,12 @@ static int64_t record_bytes(const stap_plan_s* pl, int H, int W, int64_t* st_min
     st_max = (m == 0 || o > st_max) ? o : st_max;
   }
   // the window of the sliding-window update also reaches the vectors that leave
-  for (size_t m = 0; 2 * m < pl->drem.size(); ++m) {
-    const int64_t o = (int64_t(pl->drem[2 * m]) * W + pl->drem[2 * m + 1]) * c.q;
-    st_min = std::min(st_min, o);
-    st_max = std::max(st_max, o);
-  }
+  for (int mv = 0; mv < 3; ++mv)
+    for (size_t m = 0; 2 * m < pl->drem[mv].size(); ++m) {
+      const int64_t o = (int64_t(pl->drem[mv][2 * m]) * W + pl->drem[mv][2 * m + 1]) * c.q;
+      st_min = std::min(st_min, o);
+      st_max = std::max(st_max, o);
+    }
   const int pq = c.p * c.q;
   int span = 0;
   for (int row0 = 0; row0 < pq; row0 += 16) {
@@ -160,10 +161,12 @@ stap_status fill_params(const stap_plan_s* pl, const void* x, int H, int W, ksta
   int64_t st_min = 0;
   const int64_t rec = record_bytes(pl, H, W, &st_min);
   k->st_min = int32_t(st_min);
-  k->nadd = pl->dadd.empty() ? -1 : int32_t(pl->dadd.size() / 2);
-  k->nrem = pl->dadd.empty() ? -1 : int32_t(pl->drem.size() / 2);
-  for (size_t m = 0; m < pl->dadd.size(); ++m) k->dadd[m] = int16_t(pl->dadd[m]);
-  for (size_t m = 0; m < pl->drem.size(); ++m) k->drem[m] = int16_t(pl->drem[m]);
+  for (int mv = 0; mv < 3; ++mv) {
+    k->nadd[mv] = pl->dadd[0].empty() ? -1 : int32_t(pl->dadd[mv].size() / 2);
+    k->nrem[mv] = pl->dadd[0].empty() ? -1 : int32_t(pl->drem[mv].size() / 2);
+    for (size_t m = 0; m < pl->dadd[mv].size(); ++m) k->dadd[mv][m] = int16_t(pl->dadd[mv][m]);
+    for (size_t m = 0; m < pl->drem[mv].size(); ++m) k->drem[mv][m] = int16_t(pl->drem[mv][m]);
+  }
   k->rec_bytes = uint32_t(std::min<int64_t>(rec, (int64_t(1) << 31) - 1));   // check_frame enforces < 2^31
   return STAP_OK;
 }

@@ -16,10 +16,11 @@ struct stap_plan_s {
   double tau = 0.0;
   int32_t window = 0;
   int32_t dr_min = 0, dr_max = 0, dc_min = 0, dc_max = 0;
-  // sliding-window update for a move of one pixel to the right, offsets
-  // (dr, dc) relative to the new pixel: training vectors that enter (dadd)
-  // and that leave (drem); empty when either exceeds kstap::kMaxDelta
-  std::vector<int32_t> dadd, drem;
+  // sliding-window update for a one-pixel move right, left and down
+  // (kstap::Move), offsets (dr, dc) relative to the new pixel: training
+  // vectors that enter (dadd) and that leave (drem); all empty when any list
+  // exceeds kstap::kMaxDelta
+  std::vector<int32_t> dadd[3], drem[3];
 };
 
 namespace kstap {

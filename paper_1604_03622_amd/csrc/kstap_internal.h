@@ -46,27 +46,32 @@ struct KParams {
   float2 b_s[kMaxQ];
   float2 h_s[kMaxP];
   int16_t st[2 * kMaxN];  // stencil (dr, dc)
-  // sliding-window update (run mode): from the left neighbour's S, add the
-  // nadd vectors dadd and remove the nrem vectors drem, offsets relative to
-  // the pixel; nadd < 0: always the full sum
-  int32_t nadd, nrem;
-  int16_t dadd[2 * kMaxDelta];
-  int16_t drem[2 * kMaxDelta];
+  // sliding-window update (run mode): for a one-pixel move m (kMoveRight,
+  // kMoveLeft, kMoveDown) from the previous pixel's S, add the nadd[m]
+  // vectors dadd[m] and remove the nrem[m] vectors drem[m], offsets relative
+  // to the new pixel; nadd[0] < 0: always the full sum
+  int32_t nadd[3], nrem[3];
+  int16_t dadd[3][2 * kMaxDelta];
+  int16_t drem[3][2 * kMaxDelta];
 };
 
 static_assert(sizeof(KParams) <= 4096, "KParams is passed as a kernel argument");
 
 enum Mode { kModeRun = 0, kModeProbe = 1 };
+enum Move { kMoveRight = 0, kMoveLeft = 1, kMoveDown = 2 };
 
 // Tiled visiting order of a frame's pixels.  The frame is cut into 4 x 4
 // pixel units; units are grouped into horizontal stripes 16 units (64 pixels)
 // high and, inside a stripe, taken column of units by column of units, top to
-// bottom.  Position pos = 16 * unit + 4 * (row in unit) + (column in unit).
-// A run of consecutive positions therefore covers a compact patch of the
-// frame, so the training windows of the workgroups that are in flight on one
-// XCD at the same time overlap and their snapshots are served from its L2
-// instead of being fetched again.  Positions past the right or bottom edge
-// of the frame map to no pixel.
+// bottom.  Inside a unit the order is a snake: row 0 left to right, row 1
+// right to left, and so on, so that every position after a unit's first is a
+// one-pixel move (right, left or down) from the one before it.  Position
+// pos = 16 * unit + 4 * (row in unit) + k, column k (even rows) or 3 - k (odd
+// rows).  A run of consecutive positions therefore covers a compact patch of
+// the frame, so the training windows of the workgroups that are in flight on
+// one XCD at the same time overlap and their snapshots are served from its L2
+// instead of being fetched again.  Positions past the right or bottom edge of
+// the frame map to no pixel.
 constexpr int kUnit = 4;
 constexpr int kStripeUnits = 16;
 
@@ -85,9 +90,19 @@ __host__ __device__ inline bool tiled_pixel(int64_t pos, int H, int W, int* r, i
   const int within = int(u - int64_t(s) * per_stripe);
   const int rows = (nbr - kStripeUnits * s < kStripeUnits) ? nbr - kStripeUnits * s : kStripeUnits;
   const int cb = within / rows, rb = within - cb * rows;
-  *r = (kStripeUnits * s + rb) * kUnit + k / kUnit;
-  *c = cb * kUnit + k % kUnit;
+  const int row = k / kUnit, j = k % kUnit;
+  *r = (kStripeUnits * s + rb) * kUnit + row;
+  *c = cb * kUnit + ((row & 1) ? kUnit - 1 - j : j);
   return *r < H && *c < W;
+}
+
+// The move that reaches position pos from pos - 1 (a unit's first position:
+// -1, no move).
+__host__ __device__ inline int tiled_move(int64_t pos) {
+  const int k = int(pos & (kUnit * kUnit - 1));
+  if (k == 0) return -1;
+  if (k % kUnit == 0) return kMoveDown;
+  return ((k / kUnit) & 1) ? kMoveLeft : kMoveRight;
 }
 
 // One built kernel: (p, q, r_b bound, precision) and its launchers.  The

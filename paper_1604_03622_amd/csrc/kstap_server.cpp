@@ -229,7 +229,7 @@ void stap_server_s::loop() {
     }
     if (int(ready.size()) > cap_tiles) ready.resize(cap_tiles);
     // fair-share slices of this step
-    // slices start on a 4x4 unit (runs must start on a unit row)
+    // slices start on a 4x4 unit (sliding-window chains restart on every unit)
     const int64_t share = (std::max<int64_t>(16384, step_pixels / int64_t(ready.size())) + 15) / 16 * 16;
     std::vector<kstap::KParams> descs(ready.size());
     std::map<int, std::vector<int32_t>> by_cls;
