@@ -1201,7 +1201,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       float2 a0[P * P], pt[P * P];
 #pragma unroll
       for (int e = 0; e < P * P; ++e) a0[e] = pt[e] = cz();
-      float nr = 0.f;
+      double nr = 0.0;   // exact squares of the FP32 entries, FP64 sums
 #pragma unroll
       for (int t = 0; t < NE; ++t) {
         const int e = lane + 64 * t;
@@ -1214,11 +1214,11 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
               const float2 s = sget<P, Q>(sS, i, j, k, l);
               a0[i * P + j] = cadd(a0[i * P + j], s);
               if (k == l) pt[i * P + j] = cadd(pt[i * P + j], s);
-              nr += cabs2(s);
+              nr = fma(double(s.x), double(s.x), fma(double(s.y), double(s.y), nr));
             }
         }
       }
-      normR2 = wsumd(double(nr));
+      normR2 = wsumd(nr);
       float an = 0.f;
 #pragma unroll
       for (int e = 0; e < P * P; ++e) {
@@ -1251,15 +1251,22 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 #pragma unroll
       for (int e = 0; e < P * P; ++e) anorm2 += cabs2(A[e]);
 
-      // one sweep over S: residual of (A, bv) if RES, then the new b and the
-      // partial sums of R conj(b)
+      // one sweep over S: the new b = R^T conj(a) / ||a||^2 and the partial
+      // sums of R conj(b); if RES also the residual of (A, bv) by the
+      // expansion ||R||^2 - 2 Re(a^H R conj(b)) + ||a||^2 ||b||^2, every term
+      // summed in FP64 from the FP32 entries (each product exact), so the
+      // expansion keeps the residual where it is small
       auto sweep = [&](bool res) __attribute__((always_inline)) {
         const float ainv = 1.f / anorm2;
         float2 ap[P * P];
 #pragma unroll
         for (int e = 0; e < P * P; ++e) ap[e] = cz();
         float bb = 0.f;
-        double rr = 0.0;
+        double xr = 0.0, b2 = 0.0, a2 = 0.0;
+        if (res) {
+#pragma unroll
+          for (int e = 0; e < P * P; ++e) a2 = fma(double(A[e].x), double(A[e].x), fma(double(A[e].y), double(A[e].y), a2));
+        }
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
           const int e = lane + 64 * t;
@@ -1270,16 +1277,25 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
             for (int i = 0; i < P; ++i)
 #pragma unroll
               for (int j = 0; j < P; ++j) s[i * P + j] = sget<P, Q>(sS, i, j, k, l);
+            float2 bn;
             if (res) {
-              float acc = 0.f;
+              double gx = 0.0, gy = 0.0;
 #pragma unroll
-              for (int ij = 0; ij < P * P; ++ij) acc += cabs2(csub(s[ij], cmul(A[ij], bv[t])));
-              rr += double(acc);
+              for (int ij = 0; ij < P * P; ++ij) {
+                const double ax = A[ij].x, ay = A[ij].y, sx = s[ij].x, sy = s[ij].y;
+                gx = fma(ax, sx, fma(ay, sy, gx));
+                gy = fma(ax, sy, fma(-ay, sx, gy));
+              }
+              const double bx = bv[t].x, by = bv[t].y;
+              xr = fma(bx, gx, fma(by, gy, xr));
+              b2 = fma(bx, bx, fma(by, by, b2));
+              bn = make_float2(float(gx) * ainv, float(gy) * ainv);
+            } else {
+              bn = cz();
+#pragma unroll
+              for (int ij = 0; ij < P * P; ++ij) bn = ccfma(A[ij], s[ij], bn);
+              bn = cscale(bn, ainv);
             }
-            float2 bn = cz();
-#pragma unroll
-            for (int ij = 0; ij < P * P; ++ij) bn = ccfma(A[ij], s[ij], bn);
-            bn = cscale(bn, ainv);
             bv[t] = bn;
             bb += cabs2(bn);
 #pragma unroll
@@ -1292,7 +1308,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
         const float binv = 1.f / bn2;
 #pragma unroll
         for (int ij = 0; ij < P * P; ++ij) Ap[ij] = cscale(wsum(ap[ij]), binv);
-        if (res) resid = wsumd(rr);
+        if (res) resid = fmax(normR2 + wsumd(fma(b2, a2, -2.0 * xr)), 0.0);
       };
 
       // EIG_{r_a}: A <- U (U^H A' U) U^H with U the top-r_a subspace of Herm(A')
@@ -1879,7 +1895,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     // entries (this lane: e = lane + 64 m, weight wv[m]) and reduce with DPP.
     // Optionally accumulates sum |S(i,j)_kl|^2 of the visited entries in *nr.
     // out[] is complete after the next block_sync.
-    auto block_pass = [&](const float2 (&wv)[NL], float scale, float2* out, float* nr) {
+    auto block_pass = [&](const float2 (&wv)[NL], float scale, float2* out, double* nr) {
       for (int u = 0; u < (P * P + 3) / 4; ++u) {
         const int ij = wave + 4 * u;
         if (ij >= P * P) break;   // uniform per wave
@@ -1888,7 +1904,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         const int a = up ? i : j, b = up ? j : i;
         const int base = (a * P - a * (a - 1) / 2 + (b - a)) * Q * QS;
         float2 acc = cz();
-        float n2 = 0.f;
+        double n2 = 0.0;   // exact squares of the FP32 entries, FP64 sums
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
           if (lane + 64 * m < QQ) {
@@ -1896,7 +1912,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
             float2 sv = sS[base + (up ? k * QS + l : l * QS + k)];
             sv.y = up ? sv.y : -sv.y;
             acc = ccfma(wv[m], sv, acc);
-            n2 += cabs2(sv);
+            if (nr) n2 = fma(double(sv.x), double(sv.x), fma(double(sv.y), double(sv.y), n2));
           }
         }
         if (nr) *nr += n2;
@@ -1913,9 +1929,9 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       float2 wv[NL];
 #pragma unroll
       for (int m = 0; m < NL; ++m) wv[m] = make_float2(1.f, 0.f);
-      float nr = 0.f;
+      double nr = 0.0;
       block_pass(wv, 1.f / float(QQ), sAp, &nr);
-      normR2 = block_sumd(double(nr), redd);   // its barriers also publish sAp
+      normR2 = block_sumd(nr, redd);   // its barriers also publish sAp
       float an = 0.f;
 #pragma unroll
       for (int e = 0; e < P * P; ++e) {
@@ -1953,30 +1969,48 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       float anorm2 = 0.f;
 #pragma unroll
       for (int e = 0; e < P * P; ++e) anorm2 += cabs2(A[e]);
-      // One LR-Kron half-step pair: the residual of (A, b) if RES, the new
-      // b = R^T conj(a) / ||a||^2 (lane-owned entries, all blocks), then the
-      // block pass R conj(b) / ||b||^2 into sAp.
+      // One LR-Kron half-step pair: the new b = R^T conj(a) / ||a||^2
+      // (lane-owned entries, all blocks), then the block pass R conj(b) /
+      // ||b||^2 into sAp.  If RES also the residual of (A, b) by the expansion
+      // ||R||^2 - 2 Re(a^H R conj(b)) + ||a||^2 ||b||^2, every term summed in
+      // FP64 from the FP32 entries (each product exact), so the expansion
+      // keeps the residual where it is small.
       auto sweep = [&](bool res) __attribute__((always_inline)) {
         const float ainv = 1.f / anorm2;
-        double rr = 0.0;
+        double rr = 0.0, xr = 0.0, b2 = 0.0, a2 = 0.0;
         float bb = 0.f;
+        if (res) {
+#pragma unroll
+          for (int e = 0; e < P * P; ++e) a2 = fma(double(A[e].x), double(A[e].x), fma(double(A[e].y), double(A[e].y), a2));
+        }
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
           const int e = tid + 256 * t;
           if (e < QQ) {
             const int k = e / Q, l = e - (e / Q) * Q;
-            float a2 = 0.f;
             float2 bn = cz();
+            if (res) {
+              double gx = 0.0, gy = 0.0;
 #pragma unroll
-            for (int i = 0; i < P; ++i)
+              for (int i = 0; i < P; ++i)
 #pragma unroll
-              for (int j = 0; j < P; ++j) {
-                const float2 sv = Sget(i, j, k, l);
-                if (res) a2 += cabs2(csub(sv, cmul(A[i * P + j], bv[t])));
-                bn = ccfma(A[i * P + j], sv, bn);
-              }
-            if (res) rr += double(a2);
-            bn = cscale(bn, ainv);
+                for (int j = 0; j < P; ++j) {
+                  const float2 sv = Sget(i, j, k, l);
+                  const double ax = A[i * P + j].x, ay = A[i * P + j].y, sx = sv.x, sy = sv.y;
+                  gx = fma(ax, sx, fma(ay, sy, gx));
+                  gy = fma(ax, sy, fma(-ay, sx, gy));
+                }
+              const double bx = bv[t].x, by = bv[t].y;
+              xr = fma(bx, gx, fma(by, gy, xr));
+              b2 = fma(bx, bx, fma(by, by, b2));
+              bn = make_float2(float(gx) * ainv, float(gy) * ainv);
+            } else {
+#pragma unroll
+              for (int i = 0; i < P; ++i)
+#pragma unroll
+                for (int j = 0; j < P; ++j) bn = ccfma(A[i * P + j], Sget(i, j, k, l), bn);
+              bn = cscale(bn, ainv);
+            }
             bv[t] = bn;
             bb += cabs2(bn);
             sB[e] = bn;
@@ -1984,6 +2018,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
             bv[t] = cz();
           }
         }
+        if (res) rr = fma(b2, a2, -2.0 * xr);
         // both sums through one barrier (which also publishes sB); red and
         // redd are next written after the barrier that ends this sweep
         bb = wsum(bb);
@@ -1994,7 +2029,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         }
         block_sync();
         const float bsum = (red[0] + red[1]) + (red[2] + red[3]);
-        if (res) resid = (redd[0] + redd[1]) + (redd[2] + redd[3]);
+        if (res) resid = fmax(normR2 + ((redd[0] + redd[1]) + (redd[2] + redd[3])), 0.0);
         float2 wv[NL];
 #pragma unroll
         for (int m = 0; m < NL; ++m) wv[m] = (lane + 64 * m < QQ) ? sB[lane + 64 * m] : cz();
