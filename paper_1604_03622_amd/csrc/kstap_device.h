@@ -1201,7 +1201,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       float2 a0[P * P], pt[P * P];
 #pragma unroll
       for (int e = 0; e < P * P; ++e) a0[e] = pt[e] = cz();
-      double nr = 0.0;   // exact squares of the FP32 entries, FP64 sums
+      float nr = 0.f;
 #pragma unroll
       for (int t = 0; t < NE; ++t) {
         const int e = lane + 64 * t;
@@ -1214,11 +1214,11 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
               const float2 s = sget<P, Q>(sS, i, j, k, l);
               a0[i * P + j] = cadd(a0[i * P + j], s);
               if (k == l) pt[i * P + j] = cadd(pt[i * P + j], s);
-              nr = fma(double(s.x), double(s.x), fma(double(s.y), double(s.y), nr));
+              nr += cabs2(s);
             }
         }
       }
-      normR2 = wsumd(nr);
+      normR2 = wsumd(double(nr));
       float an = 0.f;
 #pragma unroll
       for (int e = 0; e < P * P; ++e) {
@@ -1251,22 +1251,15 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 #pragma unroll
       for (int e = 0; e < P * P; ++e) anorm2 += cabs2(A[e]);
 
-      // one sweep over S: the new b = R^T conj(a) / ||a||^2 and the partial
-      // sums of R conj(b); if RES also the residual of (A, bv) by the
-      // expansion ||R||^2 - 2 Re(a^H R conj(b)) + ||a||^2 ||b||^2, every term
-      // summed in FP64 from the FP32 entries (each product exact), so the
-      // expansion keeps the residual where it is small
+      // one sweep over S: residual of (A, bv) if RES, then the new b and the
+      // partial sums of R conj(b)
       auto sweep = [&](bool res) __attribute__((always_inline)) {
         const float ainv = 1.f / anorm2;
         float2 ap[P * P];
 #pragma unroll
         for (int e = 0; e < P * P; ++e) ap[e] = cz();
         float bb = 0.f;
-        double xr = 0.0, b2 = 0.0, a2 = 0.0;
-        if (res) {
-#pragma unroll
-          for (int e = 0; e < P * P; ++e) a2 = fma(double(A[e].x), double(A[e].x), fma(double(A[e].y), double(A[e].y), a2));
-        }
+        double rr = 0.0;
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
           const int e = lane + 64 * t;
@@ -1277,25 +1270,16 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
             for (int i = 0; i < P; ++i)
 #pragma unroll
               for (int j = 0; j < P; ++j) s[i * P + j] = sget<P, Q>(sS, i, j, k, l);
-            float2 bn;
             if (res) {
-              double gx = 0.0, gy = 0.0;
+              float acc = 0.f;
 #pragma unroll
-              for (int ij = 0; ij < P * P; ++ij) {
-                const double ax = A[ij].x, ay = A[ij].y, sx = s[ij].x, sy = s[ij].y;
-                gx = fma(ax, sx, fma(ay, sy, gx));
-                gy = fma(ax, sy, fma(-ay, sx, gy));
-              }
-              const double bx = bv[t].x, by = bv[t].y;
-              xr = fma(bx, gx, fma(by, gy, xr));
-              b2 = fma(bx, bx, fma(by, by, b2));
-              bn = make_float2(float(gx) * ainv, float(gy) * ainv);
-            } else {
-              bn = cz();
-#pragma unroll
-              for (int ij = 0; ij < P * P; ++ij) bn = ccfma(A[ij], s[ij], bn);
-              bn = cscale(bn, ainv);
+              for (int ij = 0; ij < P * P; ++ij) acc += cabs2(csub(s[ij], cmul(A[ij], bv[t])));
+              rr += double(acc);
             }
+            float2 bn = cz();
+#pragma unroll
+            for (int ij = 0; ij < P * P; ++ij) bn = ccfma(A[ij], s[ij], bn);
+            bn = cscale(bn, ainv);
             bv[t] = bn;
             bb += cabs2(bn);
 #pragma unroll
@@ -1308,7 +1292,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
         const float binv = 1.f / bn2;
 #pragma unroll
         for (int ij = 0; ij < P * P; ++ij) Ap[ij] = cscale(wsum(ap[ij]), binv);
-        if (res) resid = fmax(normR2 + wsumd(fma(b2, a2, -2.0 * xr)), 0.0);
+        if (res) resid = wsumd(rr);
       };
 
       // EIG_{r_a}: A <- U (U^H A' U) U^H with U the top-r_a subspace of Herm(A')
