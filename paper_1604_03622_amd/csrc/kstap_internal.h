@@ -15,7 +15,7 @@ constexpr int kMaxRB = 8;
 constexpr int kMaxDelta = 48;   // training vectors entering (or leaving) on a one-pixel move
 
 // Everything a launch needs, passed by value as the kernel argument
-// (about 1.6 KB; the kernarg segment allows 4 KB).
+// (about 2.7 KB; the kernarg segment allows 4 KB).
 struct KParams {
   const float2* x;        // frame, complex64 [p][H][W][q]
   const uint32_t* xs;     // mixed path: BF16 split of x, hi plane then lo plane, one packed pair per sample
