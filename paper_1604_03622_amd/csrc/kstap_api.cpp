@@ -461,9 +461,9 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
   k.T = T;
   k.D = D;
   const int64_t total = kstap::tiled_positions(H, W);
-  // one 4 x 4 unit per workgroup: runs start on a unit, so the sliding-window
-  // chain (which restarts on every unit) is the same for every decomposition
-  const int64_t ppb = kstap::kUnit * kstap::kUnit;
+  // one sliding-window chain per workgroup: runs start on a chain, so the
+  // chains are the same for every decomposition
+  const int64_t ppb = (plan->cfg.p * plan->cfg.q > 64) ? kstap::kChainWide : kstap::kChainNarrow;
   k.pix_per_block = int32_t(ppb);
   k.nlogical = int32_t((total + ppb - 1) / ppb);
   const hipStream_t s = static_cast<hipStream_t>(hip_stream);
@@ -586,7 +586,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
   b->ppb = 16;
   b->grid_mult = 1;
   if (pix_per_item > 0) {
-    b->ppb = (pix_per_item + 15) / 16 * 16;   // runs start on a unit
+    b->ppb = (pix_per_item + kstap::kChainNarrow - 1) / kstap::kChainNarrow * kstap::kChainNarrow;   // runs start on a chain
   } else {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(b->signature);
@@ -652,7 +652,7 @@ stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best
     hipEventDestroy(e0);
     return fail(STAP_ERR_DEVICE, "event create failed");
   }
-  const int ppbs[] = {16, 32, 64};
+  const int ppbs[] = {16, 32, 64};   // multiples of kstap::kChainNarrow
   const int mults[] = {1, 2};
   double best = 1e300;
   int bp = batch->ppb, bm = batch->grid_mult;

@@ -1138,12 +1138,12 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
                                            PREC ? 1e-12 : 2e-6);
   };
 
-  // Sliding window (run mode, FP32 path): every position of a 4 x 4 unit but
-  // the first is a one-pixel move from the one before it (the snake of the
-  // tiled order); such a pixel updates the previous pixel's S when this
-  // workgroup has just computed it from finite data.  A unit's first pixel
-  // takes the full sum, and runs start on a unit, so the choice is the same
-  // for every decomposition.
+  // Sliding window (run mode, FP32 path): every position of a chain but the
+  // first is a one-pixel move from the one before it (tiled_move); such a
+  // pixel updates the previous pixel's S when this workgroup has just
+  // computed it from finite data.  A chain's first pixel takes the full sum,
+  // and runs start on a chain, so the choice is the same for every
+  // decomposition.
   bool chain = false;
   for (int64_t it = 0; it < count; ++it) {
     int64_t idx;
@@ -1182,7 +1182,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     // ---------------------------------------------------------------- a2 SCM
     // (the mixed path is bound by its FP64 solves, not by the cheaper BF16
     // MFMAs, so it always takes the full sum)
-    const int mv = tiled_move(first + it);
+    const int mv = tiled_move(first + it, H, W, kChainNarrow);
     const bool slide = PREC == 0 && MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
     if constexpr (PREC == 0) {
       if (slide)
@@ -1533,10 +1533,10 @@ __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restr
 // loads of the next chunk are in flight while the waves run the MFMAs of the
 // current one.  S is kept as its upper q x q blocks S(i,j), i <= j (the lower
 // blocks are their conjugate transposes), which halves its LDS footprint, and
-// it outlives the pixel: in run mode every pixel of a 4 x 4 unit but the
-// first starts from the previous pixel's n*S (a one-pixel move along the
-// unit's snake) and stages only the training vectors that enter the stencil
-// (added) and leave it (subtracted), as the narrow FP32 kernels do.  LR-Kron sweeps run over all 256 lanes with the
+// it outlives the pixel: in run mode every pixel of a sliding-window chain
+// but the first starts from the previous pixel's n*S (a one-pixel move) and
+// stages only the training vectors that enter the stencil (added) and leave
+// it (subtracted), as the narrow FP32 kernels do.  LR-Kron sweeps run over all 256 lanes with the
 // block sums reduced across waves through LDS; the small factor-A solves are
 // computed identically by every wave.  The Hermitian time factors are queued
 // in LDS and the batched tail (a6 + a8) runs 64/q' pixels per wave on all
@@ -1734,7 +1734,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     // move inside a unit) the previous pixel's n*S plus the entering vectors
     // minus the leaving ones: list entries m < npos are added, the others
     // subtracted.
-    const int mv = tiled_move(first + itp);
+    const int mv = tiled_move(first + itp, H, W, kChainWide);
     const bool slide = MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
     const int* const list = slide ? sDel + mv * 2 * kMaxDelta : sOff;
     const int cnt = slide ? prm.nadd[mv] + prm.nrem[mv] : n;

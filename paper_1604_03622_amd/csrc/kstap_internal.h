@@ -96,13 +96,35 @@ __host__ __device__ inline bool tiled_pixel(int64_t pos, int H, int W, int* r, i
   return *r < H && *c < W;
 }
 
-// The move that reaches position pos from pos - 1 (a unit's first position:
-// -1, no move).
-__host__ __device__ inline int tiled_move(int64_t pos) {
-  const int k = int(pos & (kUnit * kUnit - 1));
-  if (k == 0) return -1;
-  if (k % kUnit == 0) return kMoveDown;
-  return ((k / kUnit) & 1) ? kMoveLeft : kMoveRight;
+// Sliding-window chains: every position but a chain's first is a one-pixel
+// move from the position before it, so its covariance can be updated from
+// that pixel's.  A chain spans one unit for the narrow kernels (16 positions:
+// short runs keep many workgroups in flight) and four units down one column
+// of units for the wide kernels (64: a wide pixel's full sum costs more).
+// Runs of positions given to a workgroup start on a chain, so the chains, and
+// the results, are the same for every decomposition of a frame.
+constexpr int kChainNarrow = kUnit * kUnit;
+constexpr int kChainWide = 4 * kUnit * kUnit;
+
+// The move that reaches position pos from pos - 1, or -1 if pos starts a chain
+// (or follows a unit at the bottom of a column of units).  Inside a unit the
+// snake makes every step a move; a unit's first pixel lies directly below the
+// previous unit's last one (row 3, column 0) unless the unit starts a column
+// of its stripe.
+__host__ __device__ inline int tiled_move(int64_t pos, int H, int W, int chain) {
+  if (pos % chain == 0) return -1;
+  const int k = int(pos % (kUnit * kUnit));
+  if (k != 0) {
+    if (k % kUnit == 0) return kMoveDown;
+    return ((k / kUnit) & 1) ? kMoveLeft : kMoveRight;
+  }
+  const int nbr = (H + kUnit - 1) / kUnit, nbc = (W + kUnit - 1) / kUnit;
+  const int64_t u = pos / (kUnit * kUnit);
+  const int64_t per_stripe = int64_t(kStripeUnits) * nbc;
+  const int s = int(u / per_stripe);
+  const int within = int(u - int64_t(s) * per_stripe);
+  const int rows = (nbr - kStripeUnits * s < kStripeUnits) ? nbr - kStripeUnits * s : kStripeUnits;
+  return (within % rows == 0) ? -1 : kMoveDown;
 }
 
 // One built kernel: (p, q, r_b bound, precision) and its launchers.  The

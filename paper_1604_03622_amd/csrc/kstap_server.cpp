@@ -229,8 +229,9 @@ void stap_server_s::loop() {
     }
     if (int(ready.size()) > cap_tiles) ready.resize(cap_tiles);
     // fair-share slices of this step
-    // slices start on a 4x4 unit (sliding-window chains restart on every unit)
-    const int64_t share = (std::max<int64_t>(16384, step_pixels / int64_t(ready.size())) + 15) / 16 * 16;
+    // slices start on a sliding-window chain
+    const int64_t share = (std::max<int64_t>(16384, step_pixels / int64_t(ready.size())) + kstap::kChainNarrow - 1) /
+                          kstap::kChainNarrow * kstap::kChainNarrow;
     std::vector<kstap::KParams> descs(ready.size());
     std::map<int, std::vector<int32_t>> by_cls;
     for (size_t i = 0; i < ready.size(); ++i) {
@@ -250,7 +251,7 @@ void stap_server_s::loop() {
     }
     lk.unlock();
     // tables: descs | order | prefix (pinned staging, one copy on the compute stream)
-    const int ppb = 16;
+    const int ppb = kstap::kChainNarrow;
     const size_t o_order = sizeof(kstap::KParams) * cap_tiles;
     const size_t o_prefix = o_order + sizeof(int32_t) * cap_tiles;
     std::memcpy(h_tables, descs.data(), sizeof(kstap::KParams) * descs.size());
