@@ -164,8 +164,8 @@ stap_status batch_build(stap_batch_s* b) {
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "graph create: %s", hipGetErrorString(e));
   unsigned long long* ctr = b->d_counters;
-  int ncls = int(b->classes.size());
-  void* reset_args[] = {&ctr, &ncls};
+  int nctr = int(b->classes.size()) * kstap::kQueues;
+  void* reset_args[] = {&ctr, &nctr};
   hipKernelNodeParams kp;
   std::memset(&kp, 0, sizeof(kp));
   kp.func = const_cast<void*>(kstap::reset_kernel());
@@ -199,7 +199,7 @@ stap_status batch_build(stap_batch_s* b) {
     const int64_t* prefix = b->d_prefix + b->prefix_base[i];
     int nt = int(c.order.size());
     int ppb = b->ppb;
-    unsigned long long* counter = b->d_counters + i;
+    unsigned long long* counter = b->d_counters + i * kstap::kQueues;
     void* args[] = {&descs, &order, &prefix, &nt, &ppb, &counter};
     hipKernelNodeParams np;
     std::memset(&np, 0, sizeof(np));
@@ -232,11 +232,11 @@ stap_status batch_launch_direct(stap_batch_s* b, hipStream_t s) {
   int le = hipSuccess;
   for (size_t i = 0; i < b->splits.size() && le == hipSuccess; ++i)
     le = kstap::launch_split(b->splits[i].x, b->splits[i].xs, b->splits[i].n, s);
-  if (le == hipSuccess) le = kstap::launch_reset(b->d_counters, int(b->classes.size()), s);
+  if (le == hipSuccess) le = kstap::launch_reset(b->d_counters, int(b->classes.size()) * kstap::kQueues, s);
   for (size_t i = 0; i < b->classes.size() && le == hipSuccess; ++i) {
     const BatchClass& c = b->classes[i];
     le = kstap::launch_persistent(c.cls, b->d_descs, b->d_order + b->order_base[i], b->d_prefix + b->prefix_base[i],
-                                  int(c.order.size()), b->ppb, b->d_counters + i, grid, s);
+                                  int(c.order.size()), b->ppb, b->d_counters + i * kstap::kQueues, grid, s);
   }
   if (le != hipSuccess) return fail(STAP_ERR_DEVICE, "batch launch: %s", hipGetErrorString(hipError_t(le)));
   return STAP_OK;
@@ -605,7 +605,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
   const size_t o_order = sizeof(kstap::KParams) * b->descs.size();
   const size_t o_prefix = (o_order + sizeof(int32_t) * n_order + 15) / 16 * 16;
   const size_t o_ctr = (o_prefix + sizeof(int64_t) * n_prefix + 15) / 16 * 16;
-  const size_t bytes = o_ctr + sizeof(unsigned long long) * b->classes.size();
+  const size_t bytes = o_ctr + sizeof(unsigned long long) * b->classes.size() * kstap::kQueues;
   hipError_t e = hipMalloc(&b->d_buf, bytes);
   if (e != hipSuccess) {
     b->d_buf = nullptr;

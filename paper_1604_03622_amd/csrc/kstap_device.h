@@ -1495,8 +1495,8 @@ __global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
 // Persistent batched kernel: every workgroup pops work items (runs of `ppb`
 // consecutive tiled-order positions of one tile's range [range_first,
 // range_end)) from a
-// device counter until the queue is empty.  Items are numbered tile after tile in the order of `order` (longest
-// tiles first); prefix[j] is the first item of order[j] (prefix[nt] = total).
+// device counters until every queue is empty (kQueues queues, see kstap_internal.h).  Items are numbered tile after
+// tile in the order of `order` (longest tiles first); prefix[j] is the first item of order[j] (prefix[nt] = total).
 template <int P, int Q, int RBM, int PREC>
 __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restrict__ descs,
                                                           const int32_t* __restrict__ order,
@@ -1505,12 +1505,22 @@ __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restr
   __shared__ __attribute__((aligned(16))) char lds[Lds<P, Q, RBM, PREC>::bytes];
   __shared__ long long s_item;
   const int64_t total = prefix[nt];
+  // queue q holds items [total q / kQueues, total (q + 1) / kQueues); start
+  // with this workgroup's XCD (dispatch is round-robin over the XCDs), then
+  // move on whenever a queue is empty: every workgroup leaves after finding
+  // all kQueues queues empty
+  int q = int(blockIdx.x % kQueues), empty = 0;
   while (true) {
-    if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter, 1ull);
+    const int64_t qlo = total * q / kQueues, qhi = total * (q + 1) / kQueues;
+    if (threadIdx.x == 0) s_item = (long long)atomicAdd(counter + q, 1ull);
     wave_sync();
-    const int64_t item = s_item;
+    const int64_t item = qlo + s_item;
     wave_sync();
-    if (item >= total) break;
+    if (item >= qhi) {
+      if (++empty == kQueues) break;
+      q = (q + 1) % kQueues;
+      continue;
+    }
     int lo = 0, hi = nt - 1;   // last j with prefix[j] <= item
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;

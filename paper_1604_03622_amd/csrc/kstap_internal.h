@@ -151,9 +151,15 @@ int launch_pixels(int p, int q, int precision, int mode, const KParams& prm, hip
 // Kernel class id of (p, q, r_b, precision), -1 if none is built.
 int kernel_class(int p, int q, int r_b, int precision);
 
+// Work queues of a persistent launch: the work items are cut into kQueues
+// contiguous ranges, one per XCD; a workgroup takes items from its own XCD's
+// range first (so the workgroups in flight on one XCD share training windows
+// in its L2), then from the others'.  A launch needs kQueues zeroed counters.
+constexpr int kQueues = 8;
+
 // Enqueues the persistent batched kernel of class `cls` over the tiles
 // descs[order[j]], j < nt, whose work items (runs of ppb pixels) are numbered
-// by prefix[] (device arrays); counter: device work counter (must be 0).
+// by prefix[] (device arrays); counter: kQueues device work counters (zero).
 int launch_persistent(int cls, const KParams* descs, const int32_t* order, const int64_t* prefix, int nt, int ppb,
                       unsigned long long* counter, int grid, hipStream_t stream);
 

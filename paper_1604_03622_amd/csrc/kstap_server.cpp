@@ -276,12 +276,12 @@ void stap_server_s::loop() {
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
     hipError_t e = hipMemcpyAsync(d_tables, h_tables, o_prefix + sizeof(int64_t) * np, hipMemcpyHostToDevice, s_comp);
-    int le = (e == hipSuccess) ? kstap::launch_reset(d_ctr, int(launches.size()), s_comp) : int(e);
+    int le = (e == hipSuccess) ? kstap::launch_reset(d_ctr, int(launches.size()) * kstap::kQueues, s_comp) : int(e);
     for (size_t c = 0; c < launches.size() && le == hipSuccess; ++c) {
       const auto& L = launches[c];
       const int nt = int(by_cls[L.first].size());
       le = kstap::launch_persistent(L.first, d_desc, d_order + L.second.first, d_prefix + L.second.second, nt, ppb,
-                                    d_ctr + c, cus * 8, s_comp);
+                                    d_ctr + c * kstap::kQueues, cus * 8, s_comp);
     }
     if (le == hipSuccess) le = hipEventRecord(ev_step, s_comp);
     // while the step runs: admit new frames, finish downloads
@@ -361,7 +361,7 @@ stap_status stap_server_create(size_t hbm_budget_bytes, int32_t max_inflight, in
   const size_t o_order = sizeof(kstap::KParams) * s->cap_tiles;
   const size_t o_prefix = o_order + sizeof(int32_t) * s->cap_tiles;
   const size_t o_ctr = (o_prefix + sizeof(int64_t) * 2 * (s->cap_tiles + 1) + 255) / 256 * 256;
-  s->tables_bytes = o_ctr + sizeof(unsigned long long) * (s->cap_tiles + 1);
+  s->tables_bytes = o_ctr + sizeof(unsigned long long) * (s->cap_tiles + 1) * kstap::kQueues;
   e = hipMalloc(&s->d_tables, s->tables_bytes);
   if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->h_tables), s->tables_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->s_copy, hipStreamNonBlocking);
