@@ -126,6 +126,28 @@ stap_status stap_plan_stencil(const stap_plan_t* plan, int32_t* out);
 stap_status stap_valid_region(const stap_plan_t* plan, int32_t H, int32_t W,
                               int32_t* r0, int32_t* r1, int32_t* c0, int32_t* c1);
 
+/* The order in which stap_run visits an H x W frame (host only; for mapping
+ * work ranges to pixels and for checking the sliding-window bookkeeping).
+ * For the positions first .. first + count - 1 of the tiled order (4 x 4
+ * pixel units in stripes 64 pixels high, a snake inside each unit; the order
+ * has ceil(H/4) * ceil(W/4) * 16 positions), writes pix[2i], pix[2i+1] =
+ * (r, c), or (-1, -1) for a position past the frame's edge, and move[i] = the
+ * one-pixel move (0 right, 1 left, 2 down) from the previous position whose
+ * covariance this position's may update, or -1 where a sliding-window chain
+ * starts (every 16 positions, every 64 for p*q > 64).  move may be NULL.
+ * Errors: INVALID_ARG (NULL, negative sizes, range outside the order). */
+stap_status stap_plan_order(const stap_plan_t* plan, int32_t H, int32_t W, int64_t first, int64_t count,
+                            int32_t* pix, int32_t* move);
+
+/* Training vectors that enter (add) and leave (rem) the stencil on a
+ * one-pixel move (0 right, 1 left, 2 down), as (dr, dc) offsets from the new
+ * pixel: the plan's sliding-window update.  *nadd = *nrem = -1 if the plan
+ * always takes the full sum (a list would exceed 48 entries).  add / rem
+ * (room for 2 * 48 int32 each) may be NULL to query the counts.
+ * Errors: INVALID_ARG. */
+stap_status stap_plan_moves(const stap_plan_t* plan, int32_t move, int32_t* nadd, int32_t* nrem, int32_t* add,
+                            int32_t* rem);
+
 /* Whole-frame pass.  x: device complex64 [p][H][W][q]; T: device float [H][W];
  * D: device uint8 [H][W] or NULL.  Every element of T (and D) is written.
  * 1 <= H, W and p*H*W*q < 2^31.  Enqueued on hip_stream (hipStream_t).

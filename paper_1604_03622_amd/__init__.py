@@ -75,6 +75,9 @@ def lib() -> ctypes.CDLL:
         "stap_plan_info": [p_, ctypes.POINTER(ctypes.c_double)] + [ctypes.POINTER(i32)] * 5,
         "stap_plan_stencil": [p_, ctypes.POINTER(i32)],
         "stap_valid_region": [p_, i32, i32] + [ctypes.POINTER(i32)] * 4,
+        "stap_plan_order": [p_, i32, i32, ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "stap_plan_moves": [p_, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                            ctypes.POINTER(i32)],
         "stap_run": [p_, p_, i32, i32, p_, p_, p_],
         "stap_probe": [p_, p_, i32, i32, p_, i32, ctypes.POINTER(StapProbeOut), p_],
         "stap_run_batch": [ctypes.POINTER(StapTile), i32, p_],
@@ -169,6 +172,30 @@ class Plan:
         out = [ctypes.c_int32() for _ in range(4)]
         _check(lib().stap_valid_region(self._h, H, W, *[ctypes.byref(v) for v in out]))
         return tuple(v.value for v in out)
+
+    def order(self, H: int, W: int, first: int = 0, count: int = None):
+        """Visiting order of stap_run: (pix [count, 2] with (-1, -1) past the
+        edge, move [count]: 0 right, 1 left, 2 down, -1 a chain start)."""
+        if count is None:
+            count = ((H + 3) // 4) * ((W + 3) // 4) * 16 - first
+        pix = np.empty((count, 2), dtype=np.int32)
+        mv = np.empty(count, dtype=np.int32)
+        p32 = ctypes.POINTER(ctypes.c_int32)
+        _check(lib().stap_plan_order(self._h, H, W, first, count, pix.ctypes.data_as(p32), mv.ctypes.data_as(p32)))
+        return pix, mv
+
+    def moves(self, move: int):
+        """Offsets (dr, dc) entering and leaving the stencil on a one-pixel
+        move (0 right, 1 left, 2 down), or None if the plan never slides."""
+        na, nr = ctypes.c_int32(), ctypes.c_int32()
+        add = np.zeros((48, 2), dtype=np.int32)
+        rem = np.zeros((48, 2), dtype=np.int32)
+        p32 = ctypes.POINTER(ctypes.c_int32)
+        _check(lib().stap_plan_moves(self._h, move, ctypes.byref(na), ctypes.byref(nr), add.ctypes.data_as(p32),
+                                     rem.ctypes.data_as(p32)))
+        if na.value < 0:
+            return None
+        return add[:na.value].copy(), rem[:nr.value].copy()
 
     def __del__(self):
         h = getattr(self, "_h", None)

@@ -451,6 +451,40 @@ stap_status stap_valid_region(const stap_plan_t* plan, int32_t H, int32_t W, int
   return ok();
 }
 
+stap_status stap_plan_order(const stap_plan_t* plan, int32_t H, int32_t W, int64_t first, int64_t count,
+                            int32_t* pix, int32_t* move) {
+  if (!plan || !pix) return fail(STAP_ERR_INVALID_ARG, "NULL argument");
+  if (H < 1 || W < 1) return fail(STAP_ERR_INVALID_ARG, "frame %d x %d", H, W);
+  const int64_t total = kstap::tiled_positions(H, W);
+  if (first < 0 || count < 0 || first + count > total)
+    return fail(STAP_ERR_INVALID_ARG, "positions [%lld, %lld) outside [0, %lld)", (long long)first,
+                (long long)(first + count), (long long)total);
+  const int chain = (plan->cfg.p * plan->cfg.q > 64) ? kstap::kChainWide : kstap::kChainNarrow;
+  for (int64_t i = 0; i < count; ++i) {
+    int r, c;
+    const bool in = kstap::tiled_pixel(first + i, H, W, &r, &c);
+    pix[2 * i] = in ? r : -1;
+    pix[2 * i + 1] = in ? c : -1;
+    if (move) move[i] = kstap::tiled_move(first + i, H, W, chain);
+  }
+  return ok();
+}
+
+stap_status stap_plan_moves(const stap_plan_t* plan, int32_t move, int32_t* nadd, int32_t* nrem, int32_t* add,
+                            int32_t* rem) {
+  if (!plan || !nadd || !nrem) return fail(STAP_ERR_INVALID_ARG, "NULL argument");
+  if (move < 0 || move > 2) return fail(STAP_ERR_INVALID_ARG, "move %d (0 right, 1 left, 2 down)", move);
+  if (plan->dadd[0].empty()) {
+    *nadd = *nrem = -1;
+    return ok();
+  }
+  *nadd = int32_t(plan->dadd[move].size() / 2);
+  *nrem = int32_t(plan->drem[move].size() / 2);
+  if (add) std::copy(plan->dadd[move].begin(), plan->dadd[move].end(), add);
+  if (rem) std::copy(plan->drem[move].begin(), plan->drem[move].end(), rem);
+  return ok();
+}
+
 stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t W, float* T, uint8_t* D,
                      void* hip_stream) {
   stap_status st = check_frame(plan, x, H, W);

@@ -97,3 +97,43 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert L.stap_server_wait(None, 1, 0, None) == 1
     assert L.stap_server_stats(None, None, None, None, None) == 1
     assert L.stap_server_destroy(None) == 0
+
+
+# --------------------------------------------- sliding-window bookkeeping
+# The kernels update a pixel's covariance from the previous pixel's when the
+# order says it is a one-pixel move; these checks pin the order and the
+# entering / leaving lists on the host, against set algebra on the stencil.
+MOVE_D = {0: (0, 1), 1: (0, -1), 2: (1, 0)}
+
+
+@pytest.mark.parametrize("p,q,H,W", [(3, 16, 64, 64), (3, 8, 37, 53), (3, 16, 130, 70), (5, 24, 70, 130),
+                                     (6, 16, 9, 5)])
+def test_order_visits_every_pixel_once_and_moves_are_neighbours(p, q, H, W):
+    plan = kstap.Plan(p=p, q=q, n=64, r_a=1, r_b=3)
+    pix, mv = plan.order(H, W)
+    inside = pix[:, 0] >= 0
+    seen = pix[inside]
+    assert len(seen) == H * W
+    assert len({(int(r), int(c)) for r, c in seen}) == H * W
+    chain = 64 if p * q > 64 else 16
+    assert np.all(mv[::chain] == -1)
+    for i in np.nonzero(mv >= 0)[0]:
+        if not (inside[i] and inside[i - 1]):
+            continue   # the kernels break the chain at the frame's edge
+        dr, dc = MOVE_D[int(mv[i])]
+        assert tuple(pix[i] - pix[i - 1]) == (dr, dc), (i, pix[i - 1], pix[i], mv[i])
+    # chains are long: only a few positions start one
+    assert np.mean(mv == -1) <= (1.5 / chain if chain == 16 else 2.5 / chain)
+
+
+@pytest.mark.parametrize("n", [64, 128, 200, 256])
+def test_move_lists_are_the_stencil_set_differences(n):
+    plan = kstap.Plan(p=3, q=16, n=n, r_a=1, r_b=4)
+    st = {tuple(map(int, o)) for o in oracle.default_stencil(n)}
+    for mv, (dr, dc) in MOVE_D.items():
+        add, rem = plan.moves(mv)
+        add = {tuple(map(int, o)) for o in add}
+        rem = {tuple(map(int, o)) for o in rem}
+        prev = {(a - dr, b - dc) for a, b in st}   # previous pixel's stencil, seen from the new pixel
+        assert add == st - prev and rem == prev - st
+        assert (prev - rem) | add == st
