@@ -1750,7 +1750,12 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     const int cnt = slide ? prm.nadd[mv] + prm.nrem[mv] : n;
     const int npos = slide ? prm.nadd[mv] : n;
     const float fn = float(n);
-    const int trow = 4 * (lane >> 4), tcol = lane & 15;
+    // this lane's row and column inside a 16 x 16 tile.  On the mixed path
+    // they are made opaque, so that the S element addresses below are computed
+    // here, per pixel, instead of being hoisted out of the pixel loop (72 more
+    // live registers there, which spilled); the FP32 path has room for them.
+    int trow = 4 * (lane >> 4), tcol = lane & 15;
+    if constexpr (PREC == 1) asm volatile("" : "+v"(trow), "+v"(tcol));
     f4 accR[MYP], accI[MYP];
 #pragma unroll
     for (int u = 0; u < MYP; ++u) {
@@ -1865,6 +1870,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     // (the staging barrier above also ends every wave's reload of the old S)
     block_sync();
     {
+      if constexpr (PREC == 1) asm volatile("" : "+v"(trow), "+v"(tcol));   // as above
       const float inv_n = 1.f / fn;
 #pragma unroll
       for (int u = 0; u < MYP; ++u) {
