@@ -868,7 +868,10 @@ __device__ __forceinline__ void scm_bf16x3(const uint32_t* hwin, const uint32_t*
   for (int sl = 0; sl < PF - 1; ++sl)
     if (ch0 + sl < nch) accumulate(ring[sl]);
   const float inv_n = 1.f / float(n);
-  const int trow = 4 * (lane >> 4), tcol = lane & 15;
+  // opaque, so that the element addresses are computed here for every pixel
+  // rather than hoisted out of the caller's pixel loop and spilled
+  int trow = 4 * (lane >> 4), tcol = lane & 15;
+  asm volatile("" : "+v"(trow), "+v"(tcol));
   int t = 0;
 #pragma unroll
   for (int I = 0; I < NB; ++I)
