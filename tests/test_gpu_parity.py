@@ -156,7 +156,7 @@ def test_probe_subspaces_and_iterations():
     T_probe = pr["T"].cpu().numpy()
     assert rel_err(T_probe[g], ref["T"][g]).max() <= TOL
     # the probe runs the frame pass's body on single pixels; the frame pass
-    # may update a left neighbour's covariance instead of summing all n
+    # may update the previous pixel's covariance instead of summing all n
     # vectors, which changes only the FP32 summation order
     assert rel_err(T_probe, T_run.cpu().numpy()[pix[:, 0], pix[:, 1]]).max() <= 2e-5
     UA = pr["U_A"].cpu().numpy().astype(np.complex128)
@@ -340,7 +340,7 @@ def test_wide_pixel_parity(case):
     dB = np.abs(UB @ np.conj(np.swapaxes(UB, 1, 2)) - out["U_B"][sel] @ np.conj(np.swapaxes(out["U_B"][sel], 1, 2))).max()
     UA = pr["U_A"].cpu().numpy().astype(np.complex128)
     dA = np.abs(UA @ np.conj(np.swapaxes(UA, 1, 2)) - out["U_A"][sel] @ np.conj(np.swapaxes(out["U_A"][sel], 1, 2))).max()
-    # the frame pass updates most covariances from the left neighbour's, the
+    # the frame pass updates most covariances from the previous pixel's, the
     # probe sums every pixel's from scratch: they differ by summation order
     eP = rel_err(pr["T"].cpu().numpy(), Tg[pix[:, 0], pix[:, 1]]).max()
     note(f"[wide {case}] probe projector distance A {dA:.2e} B {dB:.2e}, probe vs frame T {eP:.2e}")
