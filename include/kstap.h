@@ -108,6 +108,9 @@ stap_status stap_config_default(stap_config* cfg);
  * OUT_OF_MEMORY. */
 stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out);
 
+/* The same call under the short name of the stap_plan / stap_run pair. */
+stap_status stap_plan(const stap_config* cfg, stap_plan_t** out);
+
 /* Frees a plan (NULL is accepted).  The plan must not be in use by work that
  * is still enqueued. */
 stap_status stap_plan_destroy(stap_plan_t* plan);

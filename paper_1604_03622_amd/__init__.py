@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
     sigs = {
         "stap_config_default": [ctypes.POINTER(StapConfig)],
         "stap_plan_create": [ctypes.POINTER(StapConfig), ctypes.POINTER(p_)],
+        "stap_plan": [ctypes.POINTER(StapConfig), ctypes.POINTER(p_)],
         "stap_plan_destroy": [p_],
         "stap_plan_info": [p_, ctypes.POINTER(ctypes.c_double)] + [ctypes.POINTER(i32)] * 5,
         "stap_plan_stencil": [p_, ctypes.POINTER(i32)],

@@ -415,6 +415,8 @@ stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out) {
   return ok();
 }
 
+stap_status stap_plan(const stap_config* cfg, stap_plan_t** out) { return stap_plan_create(cfg, out); }
+
 stap_status stap_plan_destroy(stap_plan_t* plan) {
   delete plan;
   return ok();
