@@ -86,15 +86,15 @@ stap_status planes_acquire(const stap_plan_s* plan, const void* x, int H, int W,
   if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "split planes: %s", hipGetErrorString(e));
   const int le = kstap::launch_split(static_cast<const float2*>(x), static_cast<uint32_t*>(xs), n, s);
   if (le != hipSuccess) {
-    hipFreeAsync(xs, s);
+    (void)hipFreeAsync(xs, s);   // the launch error is the one reported
     return fail(STAP_ERR_DEVICE, "split launch: %s", hipGetErrorString(hipError_t(le)));
   }
   k->xs = static_cast<const uint32_t*>(xs);
   return STAP_OK;
 }
 
-void planes_release(const kstap::KParams& k, hipStream_t s) {
-  if (k.xs) hipFreeAsync(const_cast<uint32_t*>(k.xs), s);
+hipError_t planes_release(const kstap::KParams& k, hipStream_t s) {
+  return k.xs ? hipFreeAsync(const_cast<uint32_t*>(k.xs), s) : hipSuccess;
 }
 
 }  // namespace
@@ -127,8 +127,8 @@ struct stap_batch_s {
 namespace {
 
 void batch_release_graph(stap_batch_s* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
 }
@@ -166,8 +166,7 @@ stap_status batch_build(stap_batch_s* b) {
   unsigned long long* ctr = b->d_counters;
   int nctr = int(b->classes.size()) * kstap::kQueues;
   void* reset_args[] = {&ctr, &nctr};
-  hipKernelNodeParams kp;
-  std::memset(&kp, 0, sizeof(kp));
+  hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(kstap::reset_kernel());
   kp.gridDim = dim3(1);
   kp.blockDim = dim3(64);
@@ -179,8 +178,7 @@ stap_status batch_build(stap_batch_s* b) {
   for (size_t i = 0; i < b->splits.size() && e == hipSuccess; ++i) {
     stap_batch_s::Split sp = b->splits[i];
     void* sargs[] = {&sp.x, &sp.xs, &sp.n};
-    hipKernelNodeParams sn;
-    std::memset(&sn, 0, sizeof(sn));
+    hipKernelNodeParams sn{};
     sn.func = const_cast<void*>(kstap::split_kernel());
     sn.gridDim = dim3(kstap::split_grid(sp.n));
     sn.blockDim = dim3(256);
@@ -201,8 +199,7 @@ stap_status batch_build(stap_batch_s* b) {
     int ppb = b->ppb;
     unsigned long long* counter = b->d_counters + i * kstap::kQueues;
     void* args[] = {&descs, &order, &prefix, &nt, &ppb, &counter};
-    hipKernelNodeParams np;
-    std::memset(&np, 0, sizeof(np));
+    hipKernelNodeParams np{};
     np.func = const_cast<void*>(kstap::persistent_kernel(c.cls));
     np.gridDim = dim3(grid);
     np.blockDim = dim3(64);
@@ -213,7 +210,7 @@ stap_status batch_build(stap_batch_s* b) {
     e = hipGraphAddKernelNode(&node, g, &reset_node, 1, &np);
   }
   if (e != hipSuccess) {
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return fail(STAP_ERR_DEVICE, "graph nodes: %s", hipGetErrorString(e));
   }
   b->graph = g;
@@ -245,8 +242,8 @@ stap_status batch_launch_direct(stap_batch_s* b, hipStream_t s) {
 void batch_free(stap_batch_s* b) {
   if (!b) return;
   batch_release_graph(b);
-  if (b->d_buf) hipFree(b->d_buf);
-  if (b->d_planes) hipFree(b->d_planes);
+  if (b->d_buf) (void)hipFree(b->d_buf);
+  if (b->d_planes) (void)hipFree(b->d_planes);
   delete b;
 }
 
@@ -506,9 +503,10 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
   st = planes_acquire(plan, x, H, W, &k, s);
   if (st != STAP_OK) return st;
   const int e = kstap::launch_pixels(plan->cfg.p, plan->cfg.q, plan->cfg.precision, kstap::kModeRun, k, s);
-  planes_release(k, s);
+  const hipError_t fe = planes_release(k, s);
   if (e != hipSuccess)
     return fail(STAP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  if (fe != hipSuccess) return fail(STAP_ERR_DEVICE, "split planes release: %s", hipGetErrorString(fe));
   return ok();
 }
 
@@ -534,9 +532,10 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
   st = planes_acquire(plan, x, H, W, &k, s);
   if (st != STAP_OK) return st;
   const int e = kstap::launch_pixels(plan->cfg.p, plan->cfg.q, plan->cfg.precision, kstap::kModeProbe, k, s);
-  planes_release(k, s);
+  const hipError_t fe = planes_release(k, s);
   if (e != hipSuccess)
     return fail(STAP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
+  if (fe != hipSuccess) return fail(STAP_ERR_DEVICE, "split planes release: %s", hipGetErrorString(fe));
   return ok();
 }
 
@@ -685,7 +684,7 @@ stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return fail(STAP_ERR_DEVICE, "event create failed");
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return fail(STAP_ERR_DEVICE, "event create failed");
   }
   const int ppbs[] = {16, 32, 64};   // multiples of kstap::kChainNarrow
@@ -719,8 +718,8 @@ stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best
     }
     if (st != STAP_OK) break;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (st != STAP_OK) return st;
   batch->ppb = bp;
   batch->grid_mult = bm;

@@ -204,8 +204,25 @@ void stap_server_s::poll_downloads_locked() {
 }
 
 void stap_server_s::loop() {
-  hipSetDevice(device);
+  const hipError_t de = hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
+  if (de != hipSuccess) {
+    // the worker cannot use the device: every frame fails (none is admitted,
+    // so none holds arena memory)
+    fatal = hipGetErrorString(de);
+    while (!(stop && pending.empty())) {
+      while (!pending.empty()) {
+        Frame* f = pending.front();
+        pending.pop_front();
+        f->status = STAP_ERR_DEVICE;
+        f->state = kFailed;
+        f->t_done = now_s();
+      }
+      cv_done.notify_all();
+      cv_work.wait_for(lk, std::chrono::microseconds(200));
+    }
+    return;
+  }
   while (true) {
     admit_locked();
     poll_downloads_locked();
@@ -274,7 +291,7 @@ void stap_server_s::loop() {
       h_prefix[np++] = acc;
     }
     int cus = 256;
-    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);   // else 256
     hipError_t e = hipMemcpyAsync(d_tables, h_tables, o_prefix + sizeof(int64_t) * np, hipMemcpyHostToDevice, s_comp);
     int le = (e == hipSuccess) ? kstap::launch_reset(d_ctr, int(launches.size()) * kstap::kQueues, s_comp) : int(e);
     for (size_t c = 0; c < launches.size() && le == hipSuccess; ++c) {
@@ -341,12 +358,12 @@ stap_status stap_server_create(size_t hbm_budget_bytes, int32_t max_inflight, in
   s->step_pixels = step_pixels > 0 ? step_pixels : (int64_t(1) << 20);
   s->cap_tiles = max_inflight;
   auto cleanup = [s]() {
-    if (s->ev_step) hipEventDestroy(s->ev_step);
-    if (s->s_copy) hipStreamDestroy(s->s_copy);
-    if (s->s_comp) hipStreamDestroy(s->s_comp);
-    if (s->d_tables) hipFree(s->d_tables);
-    if (s->h_tables) hipHostFree(s->h_tables);
-    if (s->arena_base) hipFree(s->arena_base);
+    if (s->ev_step) (void)hipEventDestroy(s->ev_step);
+    if (s->s_copy) (void)hipStreamDestroy(s->s_copy);
+    if (s->s_comp) (void)hipStreamDestroy(s->s_comp);
+    if (s->d_tables) (void)hipFree(s->d_tables);
+    if (s->h_tables) (void)hipHostFree(s->h_tables);
+    if (s->arena_base) (void)hipFree(s->arena_base);
     delete s->arena;
     delete s;
   };
@@ -411,15 +428,15 @@ stap_status stap_server_submit(stap_server_t* srv, const stap_plan_t* plan, cons
   }
   if (hipEventCreateWithFlags(&f->ev_up, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&f->ev_down, hipEventDisableTiming) != hipSuccess) {
-    if (f->ev_up) hipEventDestroy(f->ev_up);
+    if (f->ev_up) (void)hipEventDestroy(f->ev_up);
     delete f;
     return fail(STAP_ERR_DEVICE, "event creation failed");
   }
   {
     std::lock_guard<std::mutex> lk(srv->mu);
     if (srv->stop) {
-      hipEventDestroy(f->ev_up);
-      hipEventDestroy(f->ev_down);
+      (void)hipEventDestroy(f->ev_up);
+      (void)hipEventDestroy(f->ev_down);
       delete f;
       return fail(STAP_ERR_INVALID_ARG, "server is shutting down");
     }
@@ -449,8 +466,8 @@ stap_status stap_server_wait(stap_server_t* srv, uint64_t ticket, int32_t timeou
   const stap_status st = f->status;
   if (latency_s) *latency_s = f->t_done - f->t_submit;
   srv->frames.erase(it);
-  hipEventDestroy(f->ev_up);
-  hipEventDestroy(f->ev_down);
+  (void)hipEventDestroy(f->ev_up);
+  (void)hipEventDestroy(f->ev_down);
   delete f;
   if (st != STAP_OK) return fail(st, "frame %llu failed: %s", (unsigned long long)ticket, srv->fatal.c_str());
   return ok();
@@ -482,19 +499,20 @@ stap_status stap_server_destroy(stap_server_t* srv) {
   }
   srv->cv_work.notify_all();
   if (srv->worker.joinable()) srv->worker.join();
-  hipStreamSynchronize(srv->s_copy);
-  hipStreamSynchronize(srv->s_comp);
+  (void)hipStreamSynchronize(srv->s_copy);
+  (void)hipStreamSynchronize(srv->s_comp);
+  // teardown: failures here leave nothing to report to
   for (auto& kv : srv->frames) {
-    hipEventDestroy(kv.second->ev_up);
-    hipEventDestroy(kv.second->ev_down);
+    (void)hipEventDestroy(kv.second->ev_up);
+    (void)hipEventDestroy(kv.second->ev_down);
     delete kv.second;
   }
-  hipEventDestroy(srv->ev_step);
-  hipStreamDestroy(srv->s_copy);
-  hipStreamDestroy(srv->s_comp);
-  hipFree(srv->d_tables);
-  hipHostFree(srv->h_tables);
-  hipFree(srv->arena_base);
+  (void)hipEventDestroy(srv->ev_step);
+  (void)hipStreamDestroy(srv->s_copy);
+  (void)hipStreamDestroy(srv->s_comp);
+  (void)hipFree(srv->d_tables);
+  (void)hipHostFree(srv->h_tables);
+  (void)hipFree(srv->arena_base);
   delete srv->arena;
   delete srv;
   return ok();
