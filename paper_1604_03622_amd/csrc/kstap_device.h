@@ -1327,11 +1327,11 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
               A[i * P + j] = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
               anorm2 += cabs2(A[i * P + j]);
             }
-          if (lane < P) {
-            EC s = czero<EC>();
+          // one lane writes U_A with static indices (a lane-indexed select
+          // over ua[] is compiled into a scratch array)
+          if (lane == 0) {
 #pragma unroll
-            for (int i = 0; i < P; ++i) s = (i == lane) ? ua[i] : s;
-            sUA[lane * RAM] = s;
+            for (int i = 0; i < P; ++i) sUA[i * RAM] = ua[i];
           }
           wave_sync();
           return;
@@ -1360,14 +1360,12 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
           float2 mrow[P];
 #pragma unroll
           for (int j = 0; j < P; ++j) mrow[j] = sA[(lane < P ? lane : 0) * P + j];
+          // this lane's row of the warm start, read from LDS (a lane-indexed
+          // select over Vb would be compiled into a scratch array)
           EC va[RAM];
 #pragma unroll
-          for (int c = 0; c < RAM; ++c) {
-            EC sel = czero<EC>();
-#pragma unroll
-            for (int i = 0; i < P; ++i) sel = (i == lane) ? Vb[c][i] : sel;
-            va[c] = sel;
-          }
+          for (int c = 0; c < RAM; ++c) va[c] = (!cold && lane < P) ? sUA[lane * RAM + c] : czero<EC>();
+          wave_sync();   // sUA is rewritten below
           group_subspace<RAM, 64, P, EC>(mrow, lane < P, r_a, va, sAh, cold, 500, PREC ? 1e-12 : 2e-6);
           // every lane gathers the whole basis from LDS
           if (lane < P) {
