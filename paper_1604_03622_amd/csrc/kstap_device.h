@@ -509,13 +509,40 @@ __device__ __forceinline__ void sput(float2* sS, int a, int b, float2 v) {
   if (ba == bb) sS[sblk<P, Q>(ba, bb) + kb * (Q + 1) + ka] = make_float2(v.x, -v.y);
 }
 
+// Block sums of S and the lane's part of ||S||_F^2, gathered while S is
+// stored (for q a multiple of 16, where every 16 x 16 tile lies in one q x q
+// block): a0[i*P + j] = sum_kl S(i,j)_kl for i <= j (a lower block's sum is
+// the conjugate), each element counted with its mirror.
+template <int P>
+struct SSums {
+  float2 a0[P * P];
+  float nr;
+};
+template <int P, int Q>
+__device__ __forceinline__ void ssums_add(SSums<P>& ss, int I, int J, int row, int col, float2 v) {
+  if constexpr (Q % 16 == 0) {
+    const int bi = (16 * I) / Q, bj = (16 * J) / Q;   // constants once the tile loops unroll
+    const float m = cabs2(v);
+    if (bi != bj) {
+      ss.a0[bi * P + bj] = cadd(ss.a0[bi * P + bj], v);
+      ss.nr += 2.f * m;
+    } else if (row != col) {
+      ss.a0[bi * P + bi].x += 2.f * v.x;   // v + conj(v)
+      ss.nr += 2.f * m;
+    } else {
+      ss.a0[bi * P + bi] = cadd(ss.a0[bi * P + bi], v);
+      ss.nr += m;
+    }
+  }
+}
+
 // ------------------------------------------------------------ a2, FP32
 // S = (1/n) sum_m x_m x_m^H of one pixel on v_mfma_f32_16x16x4_f32, written
 // to LDS as the full Hermitian pq x pq matrix (row-major).
 template <int P, int Q>
 __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint32_t rec, const uint32_t* sOffB,
                                          const uint32_t (&loff)[(P * Q + 15) / 16], int n, float2* sS,
-                                         float* sP) {
+                                         float* sP, SSums<P>& ss) {
   constexpr int PQ = P * Q;
   constexpr int NB = (PQ + 15) / 16;
   constexpr int NT = NB * (NB + 1) / 2;
@@ -631,6 +658,7 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
               const float im = (J > I) ? accI[u][q4] * inv_n
                                        : (accD[I][q4] - sP[(I * 16 + tcol) * 16 + trow + q4]) * inv_n;
               sput<P, Q>(sS, row, col, make_float2(re, im));
+              ssums_add<P, Q>(ss, I, J, row, col, make_float2(re, im));
             }
           }
           if (J > I) ++u;
@@ -649,7 +677,8 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
 template <int P, int Q>
 __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane, uint32_t rec,
                                                const uint32_t* sAdd, int nadd, const uint32_t* sRem, int nrem,
-                                               const uint32_t (&loff)[(P * Q + 15) / 16], int n, float2* sS) {
+                                               const uint32_t (&loff)[(P * Q + 15) / 16], int n, float2* sS,
+                                               SSums<P>& ss) {
   constexpr int PQ = P * Q;
   constexpr int NB = (PQ + 15) / 16;
   constexpr int NT = NB * (NB + 1) / 2;
@@ -730,8 +759,11 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           const int row = 16 * I + trow + q4, col = 16 * J + tcol;
-          if (row < PQ && col < PQ && row <= col)
-            sput<P, Q>(sS, row, col, make_float2(accR[t][q4] * inv_n, ((J > I) ? accI[u][q4] : accD[I][q4]) * inv_n));
+          if (row < PQ && col < PQ && row <= col) {
+            const float2 v = make_float2(accR[t][q4] * inv_n, ((J > I) ? accI[u][q4] : accD[I][q4]) * inv_n);
+            sput<P, Q>(sS, row, col, v);
+            ssums_add<P, Q>(ss, I, J, row, col, v);
+          }
         }
         if (J > I) ++u;
         ++t;
@@ -1187,12 +1219,19 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     // MFMAs, so it always takes the full sum)
     const int mv = tiled_move(first + it, H, W, kChainNarrow);
     const bool slide = PREC == 0 && MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
+    // FP32 path, q a multiple of 16: the block sums and ||S||^2 of a4 are
+    // gathered while S is stored
+    constexpr bool kSums = PREC == 0 && Q % 16 == 0;
+    SSums<P> ss;
+#pragma unroll
+    for (int e = 0; e < P * P; ++e) ss.a0[e] = cz();
+    ss.nr = 0.f;
     if constexpr (PREC == 0) {
       if (slide)
         scm_fp32_delta<P, Q>(prm.x + win, plane, prm.rec_bytes, sDelta + 2 * mv * KD, prm.nadd[mv],
-                             sDelta + (2 * mv + 1) * KD, prm.nrem[mv], loff, n, sS);
+                             sDelta + (2 * mv + 1) * KD, prm.nrem[mv], loff, n, sS, ss);
       else
-        scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS, reinterpret_cast<float*>(sBT));
+        scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS, reinterpret_cast<float*>(sBT), ss);
     } else {
       scm_bf16x3<P, Q>(prm.xs + win, prm.xs + P * plane + win, plane, prm.rec_bytes / 2, sOffB, loff, n, sS);
     }
@@ -1201,36 +1240,59 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     float2 A[P * P];
     double normR2;
     {
-      float2 a0[P * P], pt[P * P];
+      float2 a0[P * P];
+      if constexpr (kSums) {
+        normR2 = wsumd(double(ss.nr));
 #pragma unroll
-      for (int e = 0; e < P * P; ++e) a0[e] = pt[e] = cz();
-      float nr = 0.f;
+        for (int i = 0; i < P; ++i)
 #pragma unroll
-      for (int t = 0; t < NE; ++t) {
-        const int e = lane + 64 * t;
-        if (e < QQ) {
-          const int k = e / Q, l = e - (e / Q) * Q;
+          for (int j = i; j < P; ++j) {
+            a0[i * P + j] = cscale(wsum(ss.a0[i * P + j]), 1.f / float(QQ));
+            if (j > i) a0[j * P + i] = cconj(a0[i * P + j]);
+          }
+      } else {
 #pragma unroll
-          for (int i = 0; i < P; ++i)
+        for (int e = 0; e < P * P; ++e) a0[e] = cz();
+        float nr = 0.f;
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-              const float2 s = sget<P, Q>(sS, i, j, k, l);
-              a0[i * P + j] = cadd(a0[i * P + j], s);
-              if (k == l) pt[i * P + j] = cadd(pt[i * P + j], s);
-              nr += cabs2(s);
-            }
+        for (int t = 0; t < NE; ++t) {
+          const int e = lane + 64 * t;
+          if (e < QQ) {
+            const int k = e / Q, l = e - (e / Q) * Q;
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+#pragma unroll
+              for (int j = 0; j < P; ++j) {
+                const float2 s = sget<P, Q>(sS, i, j, k, l);
+                a0[i * P + j] = cadd(a0[i * P + j], s);
+                nr += cabs2(s);
+              }
+          }
         }
+        normR2 = wsumd(double(nr));
+#pragma unroll
+        for (int e = 0; e < P * P; ++e) a0[e] = cscale(wsum(a0[e]), 1.f / float(QQ));
       }
-      normR2 = wsumd(double(nr));
       float an = 0.f;
 #pragma unroll
       for (int e = 0; e < P * P; ++e) {
-        a0[e] = cscale(wsum(a0[e]), 1.f / float(QQ));
+        A[e] = a0[e];
         an += cabs2(a0[e]);
       }
-#pragma unroll
-      for (int e = 0; e < P * P; ++e) A[e] = a0[e];
       if (double(an) <= 1e-24 * normR2) {   // fallback: partial trace R vec(I_q) (uniform branch)
+        float2 pt[P * P];
+#pragma unroll
+        for (int e = 0; e < P * P; ++e) pt[e] = cz();
+#pragma unroll
+        for (int t = 0; t < NE; ++t) {
+          const int e = lane + 64 * t;
+          if (e < QQ && e / Q == e - (e / Q) * Q) {
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+#pragma unroll
+              for (int j = 0; j < P; ++j) pt[i * P + j] = cadd(pt[i * P + j], sget<P, Q>(sS, i, j, e / Q, e / Q));
+          }
+        }
 #pragma unroll
         for (int e = 0; e < P * P; ++e) A[e] = wsum(pt[e]);
       }
