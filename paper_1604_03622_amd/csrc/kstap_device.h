@@ -818,7 +818,7 @@ __device__ __forceinline__ uint32_t hi_halves(uint32_t a, uint32_t b) { return _
 template <int P, int Q>
 __device__ __forceinline__ void scm_bf16x3(const uint32_t* hwin, const uint32_t* lwin, int64_t plane, uint32_t rec,
                                            const uint32_t* sOffB, const uint32_t (&loff)[(P * Q + 15) / 16], int n,
-                                           float2* sS) {
+                                           float2* sS, SSums<P>& ss) {
   constexpr int PQ = P * Q;
   constexpr int NB = (PQ + 15) / 16;
   constexpr int NT = NB * (NB + 1) / 2;
@@ -912,8 +912,11 @@ __device__ __forceinline__ void scm_bf16x3(const uint32_t* hwin, const uint32_t*
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4) {
         const int row = 16 * I + trow + q4, col = 16 * J + tcol;
-        if (row < PQ && col < PQ && row <= col)
-          sput<P, Q>(sS, row, col, make_float2(accR[t][q4] * inv_n, accI[t][q4] * inv_n));
+        if (row < PQ && col < PQ && row <= col) {
+          const float2 v = make_float2(accR[t][q4] * inv_n, accI[t][q4] * inv_n);
+          sput<P, Q>(sS, row, col, v);
+          ssums_add<P, Q>(ss, I, J, row, col, v);
+        }
       }
   wave_sync();
 }
@@ -1219,9 +1222,9 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     // MFMAs, so it always takes the full sum)
     const int mv = tiled_move(first + it, H, W, kChainNarrow);
     const bool slide = PREC == 0 && MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
-    // FP32 path, q a multiple of 16: the block sums and ||S||^2 of a4 are
-    // gathered while S is stored
-    constexpr bool kSums = PREC == 0 && Q % 16 == 0;
+    // q a multiple of 16: the block sums and ||S||^2 of a4 are gathered while
+    // S is stored
+    constexpr bool kSums = Q % 16 == 0;
     SSums<P> ss;
 #pragma unroll
     for (int e = 0; e < P * P; ++e) ss.a0[e] = cz();
@@ -1233,7 +1236,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       else
         scm_fp32<P, Q>(prm.x + win, plane, prm.rec_bytes, sOffB, loff, n, sS, reinterpret_cast<float*>(sBT), ss);
     } else {
-      scm_bf16x3<P, Q>(prm.xs + win, prm.xs + P * plane + win, plane, prm.rec_bytes / 2, sOffB, loff, n, sS);
+      scm_bf16x3<P, Q>(prm.xs + win, prm.xs + P * plane + win, plane, prm.rec_bytes / 2, sOffB, loff, n, sS, ss);
     }
 
     // ------------------------------------------------ a4 init, ||R||_F = ||S||_F
