@@ -6,6 +6,7 @@ Bar (per pixel, on graded pixels):
   >= 1e-3 for both factors (elsewhere several subspaces are correct);
   detection maps identical outside the margin band |T_ref - tau| <= 1e-3 tau.
 """
+import importlib.util
 import os
 import sys
 
@@ -19,6 +20,11 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-4
+
+_gspec = importlib.util.spec_from_file_location(
+    "make_golden", os.path.join(os.path.dirname(__file__), "golden", "make_golden.py"))
+golden = importlib.util.module_from_spec(_gspec)
+_gspec.loader.exec_module(golden)
 
 
 def _kstap():
@@ -92,6 +98,41 @@ def frame_oracle(x, cfg):
 
 
 # ------------------------------------------------------------------ frames
+@pytest.mark.parametrize("name", sorted(golden.FIXTURES))
+def test_golden_fixture_parity(name):
+    """The HIP path against the oracle outputs stored under tests/golden/:
+    T from a whole-frame run and eta / iterations from the probe, at the
+    stored pixels (targets, valid-region corners, a seeded sample)."""
+    kstap = _kstap()
+    spec, seed, base, _, _ = golden.FIXTURES[name]
+    head, t = golden.read(name)
+    sc = scenegen.make_scene(spec, seed=seed)
+    assert head["x_sha256"] == golden.scene_sha256(sc.x), "scene generator changed"
+    plan = kstap.Plan(**base)
+    assert plan.tau == pytest.approx(float(head["tau"]), rel=1e-9)
+    pix = np.stack([t["r"], t["c"]], 1).astype(np.int32)
+    note(f"golden {name}: frame {spec.H}x{spec.W} and probe of {pix.shape[0]} px")
+    Tg, Dg, xd = run_frame(plan, sc.x)
+    pr = kstap.probe(plan, xd, pix)
+    torch.cuda.synchronize()
+    T_at = Tg[pix[:, 0], pix[:, 1]].astype(np.float64)
+    D_at = Dg[pix[:, 0], pix[:, 1]]
+    valid = t["iters"] > 0
+    g = valid & (t["gap_A"] >= 1e-3) & (t["gap_B"] >= 1e-3)
+    assert g.sum() >= 0.8 * g.size - 6
+    e = rel_err(T_at, t["T"])
+    note(f"[golden {name}] graded {int(g.sum())}/{g.size} max err {e[g].max():.3e}")
+    assert e[g].max() <= TOL
+    band = np.abs(t["T"] - plan.tau) <= 1e-3 * plan.tau
+    assert np.array_equal(D_at[g & ~band], t["D"][g & ~band])
+    assert np.all(T_at[~valid] == 0) and np.all(D_at[~valid] == 0)
+    it = pr["iters"].cpu().numpy()
+    eta = pr["eta"].cpu().numpy()
+    assert np.all(np.abs(it[g] - t["iters"][g]) <= 1)
+    assert np.allclose(eta[g], t["eta"][g], rtol=1e-3, atol=1e-6)
+    assert np.all(it[~valid] == 0)
+
+
 def test_tiny_frame_full_parity():
     """64 x 64, p=3, q=8, n=64 (10 x 10 window minus 3 x 3 guard), r_a=1, r_b=3."""
     kstap = _kstap()
