@@ -159,20 +159,45 @@ def test_full_frame_shape_parity(H, W):
     check_parity(Tg.ravel(), Dg.ravel(), ref, plan.tau, 1, 4, f"{H}x{W}")
 
 
-def test_full_size_frame_sampled_parity():
-    """2048 x 2048, p=3, q=16, n=200: the whole frame in one launch as the
-    benchmark runs it, checked on 1500 seeded pixels plus every target."""
+_FULL_SIZE = {
+    # name: (scene, plan / oracle configuration, precision, random pixels)
+    "full_frame_fp32": (scenegen.FULL_FRAME, dict(p=3, q=16, n=200, r_a=1, r_b=4), "fp32", 1500),
+    "full_frame_bf16x3": (scenegen.FULL_FRAME, dict(p=3, q=16, n=200, r_a=1, r_b=4), "bf16x3", 1500),
+    "mixed_fp32": (scenegen.MIXED, dict(p=5, q=24, n=256, r_a=1, r_b=4), "fp32", 600),
+    "mixed_bf16x3": (scenegen.MIXED, dict(p=5, q=24, n=256, r_a=1, r_b=4), "bf16x3", 600),
+}
+_scene_cache = {}
+
+
+def _full_size_scene(spec):
+    # the two precisions of a workload share its scene (generating the
+    # 2048 x 2048 frame takes a while); only the latest scene is kept
+    if spec not in _scene_cache:
+        _scene_cache.clear()
+        _scene_cache[spec] = scenegen.make_scene(spec)
+    return _scene_cache[spec]
+
+
+@pytest.mark.parametrize("case", list(_FULL_SIZE))
+def test_full_size_frame_sampled_parity(case):
+    """The benchmarked workloads at full size, the whole frame in one launch as
+    the benchmark runs it: 2048 x 2048, p=3, q=16, n=200 and 1024 x 1024,
+    p=5, q=24, n=256, in both precisions, checked on seeded pixels plus every
+    target and the corners of the frame and of its valid region."""
     kstap = _kstap()
-    sc = scenegen.make_scene(scenegen.FULL_FRAME)
-    cfg = oracle.OracleConfig(p=3, q=16, n=200, r_a=1, r_b=4)
-    plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4)
-    note("full frame 2048x2048 p3 q16 n200")
+    spec, base, prec, count = _FULL_SIZE[case]
+    sc = _full_size_scene(spec)
+    cfg = oracle.OracleConfig(**base)
+    plan = kstap.Plan(**base, precision=prec)
+    H, W = spec.H, spec.W
+    note(f"full size {case}: {H}x{W} p{base['p']} q{base['q']} n{base['n']} {prec}")
     Tg, Dg, _ = run_frame(plan, sc.x)
-    region = oracle.valid_region(2048, 2048, cfg.training_stencil())
-    pix = np.concatenate([scenegen.random_pixels(2048, 2048, 1500, 7, region=region), sc.targets,
-                          np.array([[0, 0], [2047, 2047], [region[0], region[2]], [region[1] - 1, region[3] - 1]])])
+    region = oracle.valid_region(H, W, cfg.training_stencil())
+    pix = np.concatenate([scenegen.random_pixels(H, W, count, 7, region=region), sc.targets,
+                          np.array([[0, 0], [H - 1, W - 1], [region[0], region[2]], [region[1] - 1, region[3] - 1]])])
     ref = oracle.kron_stap_pixels(sc.x, pix, cfg)
-    check_parity(Tg[pix[:, 0], pix[:, 1]], Dg[pix[:, 0], pix[:, 1]], ref, plan.tau, 1, 4, "2048^2 sampled")
+    check_parity(Tg[pix[:, 0], pix[:, 1]], Dg[pix[:, 0], pix[:, 1]], ref, plan.tau, base["r_a"], base["r_b"],
+                 f"{case} sampled")
     assert np.isfinite(Tg).all()
     r0, r1, c0, c1 = region
     inner = np.zeros_like(Tg, bool)
