@@ -311,7 +311,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(pixels are independent given their halo; see DESIGN.md for the multi-GPU layout)",
+              "(pixels are independent given their halo: a frame would shard into row bands, "
+              "one per GPU, each with the stencil's halo rows)",
               file=sys.stderr)
         sys.exit(2)
 
