@@ -232,8 +232,13 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
   constexpr int G = 64 / QP;
   const int lane = threadIdx.x & 63, g = lane / QP, k = lane % QP;   // lane within its wavefront
   if (cold) {
+    // FP64 solves: recompute the start block on every call (an empty asm
+    // makes the row index opaque); hoisted out of the pixel loop, its
+    // widened values would be spilled and reloaded instead
+    int kk = k;
+    if constexpr (sizeof(S) == 8) asm volatile("" : "+v"(kk));
 #pragma unroll
-    for (int c = 0; c < RM; ++c) v[c] = (row_ok && c < r) ? cto<C>(omega(k, c)) : czero<C>();
+    for (int c = 0; c < RM; ++c) v[c] = (row_ok && c < r) ? cto<C>(omega(kk, c)) : czero<C>();
   }
   bool tested = !cold;
   bool done = false;
