@@ -1178,7 +1178,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   // ------------------------------------------------ a6 + a8 for G pixels
   auto tail = [&](int nfill) __attribute__((always_inline)) {
     tail_batch<P, Q, RBM, MODE, EC, false>(prm, Bq, tg, nfill, sQflag, sQidx, sQeta, sQit, sQUA, tail_scratch,
-                                           PREC ? 1e-12 : 2e-6);
+                                           PREC ? 1e-10 : 2e-6);
   };
 
   // Sliding window (run mode, FP32 path): every position of a chain but the
@@ -1771,7 +1771,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     for (int l = 0; l < Q; ++l) Bq[l] = own ? cconj(sHq[(slot < nfill ? slot : 0) * QQ + l * Q + tk]) : cz();
     tail_batch<P, Q, RBM, MODE, EC, true>(prm, Bq, slot, nfill, sQflag, sQidx, sQeta, sQit, sQUA,
                                           reinterpret_cast<EC*>(stage) + wave * (RBM * Q * G),
-                                          PREC ? 1e-12 : 2e-6);
+                                          PREC ? 1e-10 : 2e-6);
     block_sync();
   };
 
