@@ -70,6 +70,36 @@ def scm_flops_per_pixel(p, q, n):
     return 4.0 * n * pq * (pq + 1)
 
 
+def executed_vectors(plan, H, W, slides):
+    """Training vectors the frame pass accumulates into covariances, summed
+    over the frame's valid pixels, from the plan's visiting order and its
+    sliding-window lists: a pixel whose position continues a chain and whose
+    predecessor in the order is a valid pixel updates that pixel's n S with
+    the vectors entering and leaving the stencil; every other valid pixel sums
+    all n.  `slides` is False for kernels that always take the full sum (the
+    narrow split-BF16 kernels).  Returns (vectors, valid pixels)."""
+    pix, mv = plan.order(H, W)
+    r0, r1, c0, c1 = plan.valid_region(H, W)
+    valid = (pix[:, 0] >= r0) & (pix[:, 0] < r1) & (pix[:, 1] >= c0) & (pix[:, 1] < c1)
+    npx = int(valid.sum())
+    if not slides or plan.moves(0) is None:
+        return float(plan.n) * npx, npx
+    prev = np.concatenate([[False], valid[:-1]])
+    slide = valid & prev & (mv >= 0)
+    delta = np.zeros(3)
+    for m in range(3):
+        add, rem = plan.moves(m)
+        delta[m] = len(add) + len(rem)
+    vec = float(plan.n) * int((valid & ~slide).sum()) + float(delta[mv[slide]].sum())
+    return vec, npx
+
+
+def slides_for(plan):
+    """Whether the plan's kernel updates covariances along sliding-window
+    chains (FP32 narrow kernels and both wide kernels)."""
+    return plan.precision == "fp32" or plan.p * plan.q > 64
+
+
 # ----------------------------------------------------------- CPU baseline
 _G = {}
 
@@ -82,9 +112,27 @@ def _oracle_chunk(args):
     return hi - lo, float(np.nansum(out["T"]))
 
 
-def cpu_baseline(x, plan_kw, count, seed=123):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+# Worker processes of the CPU leg: the host cores given to one GPU (16 on the
+# measurement hosts), or fewer if fewer are available to this process.
+CPU_SHARE = 16
+
+
+def cpu_baseline(x, plan_kw, count, seed=123, single=20000):
     """Times the FP64 oracle (as it stands; not tuned) on `count` seeded valid
-    pixels of the same frame, one process per core, BLAS threads = 1."""
+    pixels of the same frame, one process per core of the host share, BLAS
+    threads = 1; then `single` of those pixels in one process (the
+    single-core rate)."""
     import oracle
     os.environ["OMP_NUM_THREADS"] = "1"
     ocfg = dict(p=plan_kw["p"], q=plan_kw["q"], n=plan_kw["n"], r_a=plan_kw["r_a"], r_b=plan_kw["r_b"])
@@ -92,7 +140,7 @@ def cpu_baseline(x, plan_kw, count, seed=123):
     region = oracle.valid_region(H, W, oracle.OracleConfig(**ocfg).training_stencil())
     pix = scenegen.random_pixels(H, W, count, seed, region=region)
     _G.update(x=x, pix=pix, ocfg=ocfg)
-    cores = min(16, len(os.sched_getaffinity(0)))
+    cores = min(CPU_SHARE, len(os.sched_getaffinity(0)))
     step = max(1, count // (cores * 4))
     chunks = [(lo, min(count, lo + step)) for lo in range(0, count, step)]
     try:
@@ -105,10 +153,17 @@ def cpu_baseline(x, plan_kw, count, seed=123):
     with ctx.Pool(cores) as pool:
         done = sum(n for n, _ in pool.map(_oracle_chunk, chunks))
     dt = time.perf_counter() - t0
+    single = min(single, count)
+    t1 = time.perf_counter()
+    _oracle_chunk((0, single))
+    dt1 = time.perf_counter() - t1
     if limiter is not None:
         limiter.unregister() if hasattr(limiter, "unregister") else None
     return dict(value=done / dt, unit="pixels/s", cores=cores, kind="oracle",
-                sample=f"{done} seeded valid pixels of the same frame, FP64 NumPy, {dt:.1f} s wall")
+                sample=f"{done} seeded valid pixels of the same frame, FP64 NumPy, {dt:.1f} s wall on {cores} "
+                       f"processes; single core: {single} of them in {dt1:.1f} s",
+                single_core_value=single / dt1, cpu_model=cpu_model(),
+                host_cores_visible=len(os.sched_getaffinity(0)))
 
 
 # ------------------------------------------------------------ system forms
@@ -128,25 +183,38 @@ def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _roofs(plan, H, W, sec, prec):
+    """Covariance work the kernel executes per second against the MFMA roof
+    of the arithmetic it runs on: FP32 MFMA for the plain path; for the
+    split-BF16 path the BF16 peak divided by its three products (the bf16x3
+    roof) and the BF16 peak itself (the stricter roof of a single product)."""
+    pq = plan.p * plan.q
+    vec, npx = executed_vectors(plan, H, W, slides_for(plan))
+    tfl = vec * 4.0 * pq * (pq + 1) / sec / 1e12
+    out = dict(vectors_per_pixel=vec / npx, executed_scm_tflops=tfl,
+               dense_equivalent_tflops=scm_flops_per_pixel(plan.p, plan.q, plan.n) * npx / sec / 1e12)
+    if prec == "bf16x3":
+        out.update(frac_bf16x3_roof=tfl / (MFMA_BF16_PEAK_TFLOPS / 3.0), frac_bf16_k1_roof=tfl / MFMA_BF16_PEAK_TFLOPS)
+    else:
+        out.update(frac_fp32_mfma_roof=tfl / MFMA_FP32_PEAK_TFLOPS)
+    return out
+
+
 def form_frame_mixed(kstap, torch, scene, steps):
     """The same full frame with split-BF16 covariance and FP64 eigensolves."""
     x = torch.from_numpy(scene.x).cuda()
     plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4, precision="bf16x3")
+    H, W = x.shape[1], x.shape[2]
     T = torch.empty(x.shape[1:3], device="cuda")
     D = torch.empty(x.shape[1:3], dtype=torch.uint8, device="cuda")
-    r0, r1, c0, c1 = plan.valid_region(x.shape[1], x.shape[2])
+    r0, r1, c0, c1 = plan.valid_region(H, W)
     sec = _timed(torch, lambda: kstap.run(plan, x, T, D), steps)
     px = (r1 - r0) * (c1 - c0)
-    flops = scm_flops_per_pixel(3, 16, 200) * px
-    return dict(workload="full frame 2048x2048 p=3 q=16 n=200, bf16x3 covariance + FP64 eigensolves",
-                pixels_per_s=px / sec, ms=sec * 1e3,
-                scm_tflops_credited=flops / sec / 1e12,
-                # the split products deliver an FP32-class covariance: against the
-                # FP32 MFMA peak, and against the BF16 peaks it executes on
-                frac_fp32_mfma_roof=(flops / sec / 1e12) / MFMA_FP32_PEAK_TFLOPS,
-                frac_bf16x3_roof=(flops / sec / 1e12) / (MFMA_BF16_PEAK_TFLOPS / 3.0),
-                frac_bf16_k1_roof=(flops / sec / 1e12) / MFMA_BF16_PEAK_TFLOPS,
-                bound="valu (FP64 solves and BF16 operand gathers; see the kernel profile)")
+    out = dict(workload="full frame 2048x2048 p=3 q=16 n=200, bf16x3 covariance + FP64 eigensolves",
+               pixels_per_s=px / sec, ms=sec * 1e3,
+               bound="valu (FP64 solves and BF16 operand gathers; see the kernel profile)")
+    out.update(_roofs(plan, H, W, sec, "bf16x3"))
+    return out
 
 
 def form_wide_mixed(kstap, torch, steps):
@@ -155,19 +223,18 @@ def form_wide_mixed(kstap, torch, steps):
     sc = scenegen.make_scene(scenegen.MIXED)
     x = torch.from_numpy(sc.x).cuda()
     del sc
+    H, W = x.shape[1], x.shape[2]
     out = dict(workload="p=5 q=24 1024x1024 complex64, n=256, r_a=1 r_b=4")
     for prec in ("fp32", "bf16x3"):
         plan = kstap.Plan(p=5, q=24, n=256, r_a=1, r_b=4, precision=prec)
         T = torch.empty(x.shape[1:3], device="cuda")
         D = torch.empty(x.shape[1:3], dtype=torch.uint8, device="cuda")
-        r0, r1, c0, c1 = plan.valid_region(x.shape[1], x.shape[2])
+        r0, r1, c0, c1 = plan.valid_region(H, W)
         px = (r1 - r0) * (c1 - c0)
         sec = _timed(torch, lambda: kstap.run(plan, x, T, D), steps)
-        tfl = scm_flops_per_pixel(5, 24, 256) * px / sec / 1e12
-        out[prec] = dict(pixels_per_s=px / sec, ms=sec * 1e3, scm_tflops_credited=tfl)
+        out[prec] = dict(pixels_per_s=px / sec, ms=sec * 1e3)
+        out[prec].update(_roofs(plan, H, W, sec, prec))
         _log(f"wide {prec}: {px / sec / 1e6:.2f} Mpx/s")
-    out["bf16x3"]["frac_bf16x3_roof"] = out["bf16x3"]["scm_tflops_credited"] / (MFMA_BF16_PEAK_TFLOPS / 3.0)
-    out["fp32"]["frac_fp32_mfma_roof"] = out["fp32"]["scm_tflops_credited"] / MFMA_FP32_PEAK_TFLOPS
     return out
 
 
@@ -363,10 +430,18 @@ def main():
     px_s = valid_px * args.steps / (ms_total / 1e3)
     det = int(D.sum().item())
 
-    flops = scm_flops_per_pixel(plan_kw["p"], plan_kw["q"], plan_kw["n"]) * valid_px
-    achieved = flops / (ms_per_step / 1e3) / 1e12
+    # roofline of the frame kernel: the covariance is the dense contraction
+    # (MFMA); credited with the work the kernel executes (vectors actually
+    # accumulated, sliding-window updates included), 4 pq (pq+1) flops per
+    # vector and pixel
     mixed = plan_kw["precision"] == "bf16x3"
-    # the split-BF16 path runs three BF16 products per FP32-equivalent product
+    pq = plan_kw["p"] * plan_kw["q"]
+    vec, npx = executed_vectors(plan, H, W, slides_for(plan))
+    assert npx == valid_px
+    flops = vec * 4.0 * pq * (pq + 1)
+    achieved = flops / (ms_per_step / 1e3) / 1e12
+    dense = scm_flops_per_pixel(plan_kw["p"], plan_kw["q"], plan_kw["n"]) * valid_px / (ms_per_step / 1e3) / 1e12
+    # the split-BF16 path runs three BF16 products per FP32-class product
     peak = MFMA_BF16_PEAK_TFLOPS / 3 if mixed else MFMA_FP32_PEAK_TFLOPS
     result = {
         "metric": "Kron-STAP output pixels/s on 1 MI355X (" +
@@ -396,8 +471,14 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / peak,
             "traffic": profiled_traffic(args.workload),   # HBM bytes per launch, rocprofv3 counters
-            "credited": "direct-definition covariance flops 4 n pq (pq+1) per valid pixel; 15 of every 16 "
-                        "covariances are updated from the previous pixel's, so fewer are executed",
+            "credited": f"executed covariance work: {vec / valid_px:.3f} training vectors per valid pixel "
+                        f"(sliding-window updates counted as the vectors they add and remove) x 4 pq (pq+1) "
+                        f"flops; one launch = {valid_px} valid pixels",
+            "vectors_per_pixel": vec / valid_px,
+            "flops_per_launch": flops,
+            "dense_equivalent_tflops": dense,
+            "dense_equivalent_note": "4 n pq (pq+1) flops per valid pixel, the direct definition of the "
+                                     "covariance; not executed by the sliding-window kernel",
         },
         "cpu_baseline": cpu,
     }

@@ -47,3 +47,49 @@ def test_profiled_traffic_stands_only_for_unchanged_sources(tmp_path, monkeypatc
     assert bench.profiled_traffic("full_frame") is None
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(tmp_path / "missing.md"))
     assert bench.profiled_traffic("full_frame") is None
+
+
+def _vectors_by_loop(plan, H, W):
+    """Executed vectors recounted position by position: a valid pixel right
+    after a valid pixel, inside a sliding-window chain, costs the size of the
+    symmetric difference of the two pixels' training sets; others cost n."""
+    pix, mv = plan.order(H, W)
+    r0, r1, c0, c1 = plan.valid_region(H, W)
+    st = {tuple(o) for o in plan.stencil.tolist()}
+    total, prev_ok, prev = 0, False, None
+    for (r, c), m in zip(pix.tolist(), mv.tolist()):
+        ok = r0 <= r < r1 and c0 <= c < c1
+        if ok:
+            if prev_ok and m >= 0:
+                a = {(r + dr, c + dc) for dr, dc in st}
+                b = {(prev[0] + dr, prev[1] + dc) for dr, dc in st}
+                total += len(a ^ b)
+            else:
+                total += plan.n
+        prev_ok, prev = ok, (r, c)
+    return total
+
+
+@pytest.mark.parametrize("H,W", [(40, 37), (64, 64)])
+def test_executed_vectors_match_a_recount(H, W):
+    import paper_1604_03622_amd as kstap
+    plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4)
+    vec, npx = bench.executed_vectors(plan, H, W, True)
+    assert vec == _vectors_by_loop(plan, H, W)
+    r0, r1, c0, c1 = plan.valid_region(H, W)
+    assert npx == (r1 - r0) * (c1 - c0)
+    assert bench.executed_vectors(plan, H, W, False) == (200.0 * npx, npx)
+
+
+def test_executed_vectors_on_the_full_frame():
+    """2048 x 2048, n = 200: a chain's first pixel sums 200 vectors, the 15
+    others 19 + 19: (200 + 15 * 38) / 16 = 48.125 vectors per pixel, up to
+    the chains cut by the valid region's edges."""
+    import paper_1604_03622_amd as kstap
+    plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4)
+    vec, npx = bench.executed_vectors(plan, 2048, 2048, True)
+    assert npx == 2033 * 2033
+    assert 48.0 <= vec / npx <= 48.6
+    assert bench.slides_for(plan)
+    assert not bench.slides_for(kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4, precision="bf16x3"))
+    assert bench.slides_for(kstap.Plan(p=5, q=24, n=256, r_a=1, r_b=4, precision="bf16x3"))

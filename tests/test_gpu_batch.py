@@ -44,14 +44,16 @@ def test_batch_equals_tiles_alone_and_oracle():
         torch.cuda.synchronize()
         assert torch.equal(T, Ta), f"tile {i}: batched T differs from the tile alone"
         assert torch.equal(D, Da), f"tile {i}: batched D differs from the tile alone"
-    for i in (0, 2, 3):
+    for i in range(len(tiles)):
         sc, cfg = refs[i]
         ref = oracle.kron_stap_frame(sc.x, oracle.OracleConfig(**cfg))
         Tg = tiles[i][2].cpu().numpy()
         pix = ref["pixels"]
         e = np.abs(Tg[pix[:, 0], pix[:, 1]] - ref["T"]) / np.maximum(ref["T"], 1.0)
         g = (oracle.relative_gaps(ref["lam_B"], cfg["r_b"]) >= 1e-3) & (oracle.relative_gaps(ref["lam_A"], cfg["r_a"]) >= 1e-3)
-        print(f"tile {i}: max err {e[g].max():.2e}", flush=True)
+        print(f"tile {i} {cfg} {tiles[i][0].precision}: graded {int(g.sum())}/{g.size} max err {e[g].max():.2e}",
+              flush=True)
+        assert g.sum() >= 0.8 * g.size
         assert e[g].max() <= 1e-4
     # launching again (graph replay) gives the same results; tuning keeps them
     T0 = [t[2].clone() for t in tiles]
@@ -77,3 +79,56 @@ def test_batch_equals_tiles_alone_and_oracle():
     kstap.run_batch(tiles)
     for t, t0 in zip(tiles, T0):
         assert torch.equal(t[2], t0)
+
+
+def test_benchmark_batch_sampled_oracle_parity():
+    """The benchmark's own 64-tile batch (sides 128..1024, q in {8, 12, 16},
+    n in {64, 128, 256}, r_a in {1, 2}, r_b in {2..6}; 20 M pixels), tuned
+    and launched as the benchmark launches it, in both precisions: every tile
+    checked against the oracle on 200 seeded valid pixels."""
+    import paper_1604_03622_amd as kstap
+    specs = scenegen.batch_tile_specs()
+    xs, outs = [], []
+    for i, (sp, n) in enumerate(specs):
+        xs.append(scenegen.make_scene_torch(sp, seed=scenegen.BASE_SEED + 100 + i))
+        outs.append((torch.empty((sp.H, sp.W), device="cuda"), torch.empty((sp.H, sp.W), dtype=torch.uint8,
+                                                                             device="cuda")))
+    torch.cuda.synchronize()
+    results = {}
+    for prec in ("fp32", "bf16x3"):
+        plans = [kstap.Plan(p=3, q=sp.q, n=n, r_a=sp.r_a, r_b=sp.r_b, precision=prec) for sp, n in specs]
+        tiles = [(pl, x, T, D) for pl, x, (T, D) in zip(plans, xs, outs)]
+        for _, _, T, D in tiles:
+            T.fill_(-1.0)
+            D.fill_(7)
+        b = kstap.Batch(tiles)
+        print(f"benchmark batch {prec}: {b.info()}, tuned {b.tune()}", flush=True)
+        for _, _, T, D in tiles:
+            T.fill_(-1.0)
+        b.launch()
+        torch.cuda.synchronize()
+        results[prec] = [(T.cpu().numpy(), D.cpu().numpy()) for _, _, T, D in tiles]
+        del b
+    worst = {"fp32": 0.0, "bf16x3": 0.0}
+    for i, (sp, n) in enumerate(specs):
+        cfg = oracle.OracleConfig(p=3, q=sp.q, n=n, r_a=sp.r_a, r_b=sp.r_b)
+        x = xs[i].cpu().numpy()
+        region = oracle.valid_region(sp.H, sp.W, cfg.training_stencil())
+        rng = np.random.Generator(np.random.PCG64(scenegen.BASE_SEED + 900 + i))
+        pix = np.stack([rng.integers(region[0], region[1], 200), rng.integers(region[2], region[3], 200)], 1)
+        ref = oracle.kron_stap_pixels(x, pix, cfg)
+        g = (ref["valid"] & (oracle.relative_gaps(ref["lam_A"], sp.r_a) >= 1e-3)
+             & (oracle.relative_gaps(ref["lam_B"], sp.r_b) >= 1e-3))
+        assert g.sum() >= 0.8 * len(pix), f"tile {i}: only {int(g.sum())} graded"
+        band = np.abs(ref["T"] - ref["tau"]) <= 1e-3 * ref["tau"]
+        for prec in ("fp32", "bf16x3"):
+            Tg, Dg = results[prec][i]
+            assert np.isfinite(Tg).all() and (Tg >= 0).all(), f"tile {i} {prec}: T not written everywhere"
+            e = np.abs(Tg[pix[:, 0], pix[:, 1]] - ref["T"]) / np.maximum(ref["T"], 1.0)
+            worst[prec] = max(worst[prec], float(e[g].max()))
+            assert e[g].max() <= 1e-4, f"tile {i} {prec}: max err {e[g].max():.2e}"
+            d = Dg[pix[:, 0], pix[:, 1]]
+            assert np.array_equal(d[g & ~band], ref["D"][g & ~band]), f"tile {i} {prec}: detections differ"
+        del x
+    print(f"benchmark batch sampled parity: worst error fp32 {worst['fp32']:.2e}, bf16x3 {worst['bf16x3']:.2e}",
+          flush=True)

@@ -28,6 +28,11 @@ MUTANTS = {
     "Algorithm 1 parenthesis": ("q * (J - p * ((J - 1) // p) - 1)", "q * (J - p * ((J - 1) // p))"),
     "ascending eigen order": ("    lam = lam[..., ::-1]\n    V = V[..., ::-1]\n", "    pass\n"),
     "final half-step without conjugate": ("bfin = _mtv(Rs, np.conj(a))", "bfin = _mtv(Rs, a)"),
+    "truncation gap one rank late": ("return (lam[..., r - 1] - lam[..., r]) / top",
+                                     "return (lam[..., r] - lam[..., min(r + 1, m - 1)]) / top"),
+    "truncation gap over the smaller eigenvalue": ("return (lam[..., r - 1] - lam[..., r]) / top",
+                                                   "return (lam[..., r - 1] - lam[..., r]) / lam[..., r - 1]"),
+    "truncation gap without its rank-0 branch": ("if r <= 0 or r >= m:", "if r >= m:"),
 }
 
 

@@ -402,3 +402,42 @@ def test_scm_hermitian_psd_trace_and_constant_field():
     assert lam[-1] == pytest.approx(np.vdot(v, v).real, rel=1e-12)
     assert abs(abs(np.vdot(U[:, -1], v)) / np.linalg.norm(v) - 1) < 1e-12
     assert np.all(np.abs(lam[:-1]) <= 1e-12 * lam[-1])
+
+
+# ---------------------------------------------------------------- R9 (graded set)
+def test_relative_gap_on_known_spectra():
+    """The truncation gap that decides which pixels are graded: for a known
+    spectrum (4, 3, 1, 0.5) the gaps after ranks 1, 2, 3 are 1/4, 2/4 and
+    0.5/4 of the largest eigenvalue (hand-computed constants), both on the
+    sorted eigenvalues directly and after a random unitary rotation of the
+    diagonal matrix through the oracle's eigensolver; ranks 0 and 4 (no
+    truncation) count as a full gap."""
+    lam = np.array([4.0, 3.0, 1.0, 0.5])
+    expect = {1: 0.25, 2: 0.5, 3: 0.125}
+    for r, g in expect.items():
+        assert oracle.relative_gaps(lam, r) == pytest.approx(g, rel=1e-15)
+    rng = np.random.default_rng(31)
+    Q = np.linalg.qr(crandn(rng, 4, 4))[0]
+    M = (Q * lam) @ Q.conj().T
+    ev, _, _ = oracle.top_eigvecs(M, 2)
+    for r, g in expect.items():
+        assert oracle.relative_gaps(ev, r) == pytest.approx(g, rel=1e-12)
+    assert oracle.relative_gaps(lam, 0) == 1.0
+    assert oracle.relative_gaps(lam, 4) == 1.0
+    # batched rows keep their own gaps
+    batch = np.array([[4.0, 3.0, 1.0, 0.5], [2.0, 2.0, 2.0, 0.0], [1.0, 0.0, 0.0, 0.0]])
+    np.testing.assert_allclose(oracle.relative_gaps(batch, 2), [0.5, 0.0, 0.0], rtol=1e-15, atol=0)
+    np.testing.assert_allclose(oracle.relative_gaps(batch, 3), [0.125, 1.0, 0.0], rtol=1e-15, atol=0)
+    np.testing.assert_array_equal(oracle.relative_gaps(batch, 0), np.ones(3))
+
+
+def test_relative_gap_flags_a_tie_at_the_truncation():
+    """A pixel whose space factor has two equal leading eigenvalues cannot be
+    graded at rank 1 (several subspaces are correct), while a clear gap passes
+    the 1e-3 bar."""
+    rng = np.random.default_rng(32)
+    Q = np.linalg.qr(crandn(rng, 3, 3))[0]
+    tie, _, _ = oracle.top_eigvecs((Q * np.array([2.0, 2.0, 0.1])) @ Q.conj().T, 1)
+    clear, _, _ = oracle.top_eigvecs((Q * np.array([2.0, 1.0, 0.1])) @ Q.conj().T, 1)
+    assert oracle.relative_gaps(tie, 1) < 1e-12
+    assert oracle.relative_gaps(clear, 1) == pytest.approx(0.5, rel=1e-12)
