@@ -265,21 +265,25 @@ def form_batch(kstap, torch):
     return res
 
 
-def form_serving(kstap, torch, nframes):
+def form_serving(kstap, torch, nframes, pool=40):
     """Poisson stream (and a burst) of frames of mixed sizes through the
     continuous-batching server vs the plain per-frame path (upload, run,
     download, one frame at a time), same arrival trace, latency = submit to
-    results in host memory."""
+    results in host memory.  The `nframes` arrivals draw from a pool of
+    `pool` distinct seeded frames (pinned host memory holds the pool, not
+    every arrival)."""
     import threading
-    trace = scenegen.serving_trace()[:nframes]
-    frames = []
+    trace = scenegen.serving_trace()[:pool]
+    pooled = []
     for i, (sp, n) in enumerate(trace):
         xd = scenegen.make_scene_torch(sp, seed=scenegen.BASE_SEED + 500 + i)
         xh = torch.empty(xd.shape, dtype=torch.complex64, pin_memory=True)
         xh.copy_(xd)
         del xd
-        frames.append((kstap.Plan(p=3, q=sp.q, n=n, r_a=1, r_b=3), xh, sp.H * sp.W,
+        pooled.append((kstap.Plan(p=3, q=sp.q, n=n, r_a=1, r_b=3), xh, sp.H * sp.W,
                        kstap.Plan(p=3, q=sp.q, n=n, r_a=1, r_b=3, precision="bf16x3")))
+    pick = np.random.Generator(np.random.PCG64(scenegen.BASE_SEED + 8)).integers(0, len(pooled), nframes)
+    frames = [pooled[k] for k in pick]
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     tot_px = sum(f[2] for f in frames)
@@ -327,9 +331,10 @@ def form_serving(kstap, torch, nframes):
     rng = np.random.Generator(np.random.PCG64(scenegen.BASE_SEED + 9))
     arr = np.cumsum(rng.exponential(1.0 / rate, len(frames)))
     arr -= arr[0]
-    out = dict(workload=f"{len(frames)} frames, side U{{256..2048}}, q in {{8,16}}, n U{{64..256}}, p=3; "
-                        f"pinned host frames, latency = submit to results in host memory",
-               frames=len(frames), mean_pixels_per_frame=mean_px,
+    out = dict(workload=f"{len(frames)} arrivals drawn from {len(pooled)} distinct frames, side U{{256..2048}}, "
+                        f"q in {{8,16}}, n U{{64..256}}, p=3; pinned host frames, latency = submit to results in "
+                        f"host memory",
+               frames=len(frames), distinct_frames=len(pooled), mean_pixels_per_frame=mean_px,
                poisson_rate_fps=rate, rate_rule="0.7 x plain-path capacity on this trace")
     for name, arrivals in (("burst", [0.0] * len(frames)), ("poisson", list(arr))):
         pl_lat, pl_span = plain(arrivals)
@@ -349,6 +354,90 @@ def form_serving(kstap, torch, nframes):
     return out
 
 
+def measured_peaks(torch):
+    """Throughput measured on this GPU with plain library operations, as lower
+    bounds of its peaks: HBM bandwidth of a 1 GiB device-to-device copy
+    (bytes read + written over time) and torch.matmul at 8192^3 in FP32 and
+    BF16 (dense GEMM on the matrix cores)."""
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    sec = _timed(torch, lambda: dst.copy_(src), 10)
+    out = dict(hbm_copy_GBps=2 * (1 << 30) / sec / 1e9)
+    del src, dst
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+        a = torch.randn((8192, 8192), device="cuda").to(dt)
+        b = torch.randn((8192, 8192), device="cuda").to(dt)
+        sec = _timed(torch, lambda: torch.matmul(a, b), 5)
+        out[f"{name}_gemm_TFLOPs"] = 2 * 8192 ** 3 / sec / 1e12
+        del a, b
+    torch.cuda.empty_cache()
+    out["note"] = "lower bounds of the hardware peaks; roofline fractions use the published peaks"
+    return out
+
+
+def form_large_q(kstap, torch, cpu=True):
+    """LR-Kron on one large covariance, the paper's timing workload: n = 5
+    snapshots, a rank-one space factor, identity time factor, p = 3 with q up
+    to 2500 and p = 6 with q up to 1250, tolerances 1e-4 and 1e-6.  Time per
+    estimate (A-hat, eta and the q x q B-hat), the solve alone, and the FP64
+    oracle on the same snapshots."""
+    import oracle.large_q as LQ
+    rows = []
+    for p, qs in ((3, (50, 250, 500, 1000, 2500)), (6, (25, 250, 1250))):
+        for q in qs:
+            X = scenegen.large_q_snapshots(p, q, 5, seed=scenegen.BASE_SEED + 1000 + q)
+            xd = torch.from_numpy(X).cuda()
+            for eps in (1e-4, 1e-6):
+                out = kstap.lrkron(xd, eps=eps)
+                torch.cuda.synchronize()
+                st = out["stats"].cpu().numpy()
+                full = _timed(torch, lambda: kstap.lrkron(xd, eps=eps), 20)
+                solve = _timed(torch, lambda: kstap.lrkron(xd, eps=eps, with_B=False), 20)
+                row = dict(p=p, q=q, n=5, eps=eps, iterations=int(st[1]), eta=float(st[0]), us_total=full * 1e6,
+                           us_solve=solve * 1e6,
+                           emit_b_GBps=q * q * 8 / max(full - solve, 1e-9) / 1e9)
+                if cpu and q <= 1000:
+                    t0 = time.perf_counter()
+                    LQ.lr_kron_snapshots(X, eps=eps)
+                    row["oracle_s"] = time.perf_counter() - t0
+                rows.append(row)
+                _log(f"large q p={p} q={q} eps={eps:g}: {full * 1e6:.1f} us ({int(st[1])} iterations)")
+    return dict(workload="one covariance from n=5 snapshots, rank-one A, B = I_q (Sec. 6.1 timing setting)",
+                rows=rows,
+                note="B-hat emission is bound by writing q^2 complex64 values; emit_b_GBps = q^2 * 8 bytes over "
+                     "(total - solve) time")
+
+
+def form_variants(kstap, torch):
+    """Statistic variants on a 1024 x 1024 p=3 q=16 frame (FP32): the plain
+    statistic, the classical projector, a 16-bin Doppler bank with the
+    enhancement image and bin map, and a two-pass 512 x 512 multipass frame
+    with its per-pass and change images."""
+    spec = scenegen.SceneSpec(p=3, q=16, H=1024, W=1024, r_a=1, r_b=4, n_targets=50, snr_db=(0.0, 15.0), block=256)
+    x = scenegen.make_scene_torch(spec, seed=scenegen.BASE_SEED + 1200)
+    base = dict(p=3, q=16, n=200, r_a=1, r_b=4)
+    plans = dict(plain=kstap.Plan(**base), classical=kstap.Plan(**base, filter="classical"),
+                 bank16_enhancement=kstap.Plan(**base, nbank=16))
+    H, W = spec.H, spec.W
+    r0, r1, c0, c1 = plans["plain"].valid_region(H, W)
+    px = (r1 - r0) * (c1 - c0)
+    out = dict(workload="1024x1024 p=3 q=16 n=200 FP32; multipass 2 x 3 channels 512x512 q=16 n=200")
+    for name, pl in plans.items():
+        sec = _timed(torch, lambda: kstap.run_ex(pl, x), 3)
+        out[name] = dict(pixels_per_s=px / sec, ms=sec * 1e3)
+        _log(f"variant {name}: {px / sec / 1e6:.1f} Mpx/s")
+    del x
+    mp = scenegen.make_multipass_scene(scenegen.MultipassSpec(passes=2, p=3, q=16, H=512, W=512, r_b=4, n_targets=20),
+                                       seed=scenegen.BASE_SEED + 1201)
+    xm = torch.from_numpy(mp.x).cuda()
+    pl = kstap.Plan(p=6, q=16, n=200, r_a=2, r_b=4, passes=2)
+    r0, r1, c0, c1 = pl.valid_region(512, 512)
+    sec = _timed(torch, lambda: kstap.run_ex(pl, xm), 3)
+    out["multipass_k2"] = dict(pixels_per_s=(r1 - r0) * (c1 - c0) / sec, ms=sec * 1e3)
+    _log(f"variant multipass: {(r1 - r0) * (c1 - c0) / sec / 1e6:.2f} Mpx/s")
+    return out
+
+
 def system_forms(kstap, torch, args, scene):
     forms = {}
     forms["frame_bf16x3"] = form_frame_mixed(kstap, torch, scene, max(3, args.steps // 2))
@@ -359,6 +448,10 @@ def system_forms(kstap, torch, args, scene):
     forms["batch"] = form_batch(kstap, torch)
     torch.cuda.empty_cache()
     forms["serving"] = form_serving(kstap, torch, args.serve_frames)
+    torch.cuda.empty_cache()
+    forms["large_q"] = form_large_q(kstap, torch, cpu=not args.no_cpu)
+    torch.cuda.empty_cache()
+    forms["variants"] = form_variants(kstap, torch)
     return forms
 
 
@@ -372,7 +465,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=400000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / served / mixed-precision legs")
-    ap.add_argument("--serve-frames", type=int, default=32)
+    ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -485,6 +578,7 @@ def main():
     if not args.no_forms:
         del x
         torch.cuda.empty_cache()
+        result["measured_peaks"] = measured_peaks(torch)
         result["forms"] = system_forms(kstap, torch, args, scene)
     print(json.dumps(result), flush=True)
 

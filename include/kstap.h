@@ -65,6 +65,11 @@ typedef enum {
   STAP_STAT_FIXED = 1   /* T for the single spatial steering h_steer */
 } stap_stat_mode;
 
+typedef enum {
+  STAP_FILTER_KRON = 0,      /* Kron-STAP projector (I - U_A U_A^H) (x) (I - U_B U_B^H), Sec. 5, Eq. (25) */
+  STAP_FILTER_CLASSICAL = 1  /* classical joint projector I - U_A U_A^H (x) U_B U_B^H, Sec. 5, Eq. (24) */
+} stap_filter;
+
 /* Detector configuration.  Fill with stap_config_default(), then override. */
 typedef struct {
   int32_t p;              /* channels, 1 <= p <= 8 */
@@ -87,6 +92,17 @@ typedef struct {
   double pfa;             /* tau = upper-tail pfa quantile of Gamma(p - r_a, 1), the null law
                              of T under white noise; 0 < pfa < 1 */
   int32_t precision;      /* stap_precision */
+  int32_t filter;         /* stap_filter.  The classical filter's statistic,
+                             ||F_A X b*||^2/||b||^2 + ||P_A X conj(F_B b)||^2/(b^H F_B b),
+                             is Gamma(p, 1) under white noise, so its default tau is
+                             that quantile */
+  int32_t nbank;          /* 0: the temporal steering b_steer.  1 <= M <= 64: a bank of
+                             M Doppler bins b_m[k] = exp(2 pi j ((m k) mod M) / M)
+                             (the steering vectors d_i of Sec. 6.3); T is the maximum
+                             over the bank (D = T > tau with the single-bin tau) */
+  int32_t passes;         /* K >= 1 registered passes stacked into the p channels,
+                             pass k in channels k*p/K .. (k+1)*p/K - 1 (Sec. 3); K > 1
+                             needs p % K == 0 and the Kron-STAP filter; use r_a = K */
 } stap_config;
 
 /* Default stencil: offsets (dr, dc) of the window [-W/2, W/2-1]^2 minus the
@@ -98,7 +114,8 @@ typedef struct stap_plan_s stap_plan_t;
 
 /* Fills *cfg with defaults: p=3, q=16, n=200, stencil=NULL, window=0,
  * guard=3, r_a=1, r_b=4, eps=1e-6, min_iter=2, max_iter=50, GLRT, b_steer=NULL,
- * h_steer=NULL, tau=0, pfa=1e-4, FP32.  Errors: INVALID_ARG if cfg is NULL. */
+ * h_steer=NULL, tau=0, pfa=1e-4, FP32, Kron-STAP filter, nbank=0, passes=1.
+ * Errors: INVALID_ARG if cfg is NULL. */
 stap_status stap_config_default(stap_config* cfg);
 
 /* Validates *cfg, builds the stencil, computes tau, and copies every host
@@ -158,6 +175,52 @@ stap_status stap_plan_moves(const stap_plan_t* plan, int32_t move, int32_t* nadd
 stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t W,
                      float* T, uint8_t* D, void* hip_stream);
 
+/* Optional outputs of stap_run_ex beside T and D (device buffers, NULL = not
+ * written).  Pixels outside the valid region get 0 in every output; pixels
+ * with non-finite data get NaN in the float outputs. */
+typedef struct {
+  float* T;        /* [H][W], required */
+  uint8_t* D;      /* [H][W] */
+  float* E;        /* [H][W] enhancement image (Sec. 6.3): T divided by channel 0's SAR
+                      intensity |sum_k X[0,k] conj(b_k)|^2 / ||b||^2 at the selected
+                      steering; 0 where that intensity is 0 */
+  uint8_t* bin;    /* [H][W] Doppler bin of the maximum (first maximiser; 0 without a bank) */
+  float* Tpass;    /* [K][H][W] per-pass images (passes K > 1): the energy of pass k's
+                      channels of F_A X conj(F_B b), over b^H F_B b (Sec. 3, Sec. 6.4) */
+  float* C;        /* [K-1][H][W] non-coherent change images sqrt(Tpass_k) - sqrt(Tpass_0),
+                      k = 1..K-1 (Sec. 6.4) */
+} stap_outputs;
+
+/* Whole-frame pass with the optional outputs above; otherwise as stap_run.
+ * Errors: INVALID_ARG (also Tpass or C requested from a one-pass plan),
+ * UNSUPPORTED, DEVICE. */
+stap_status stap_run_ex(const stap_plan_t* plan, const void* x, int32_t H, int32_t W,
+                        const stap_outputs* out, void* hip_stream);
+
+/* LR-Kron on one large covariance (the single-covariance estimation the
+ * paper times, Sec. 6.1: a few training snapshots, many azimuth samples).
+ * Algorithm 2 (Sec. 4) with the stop rule of the plan configuration, on the
+ * rearrangement (Algorithm 1) of S = (1/n) sum_m x_m x_m^H, x_m = vec(X_m^T)
+ * (Eq. (2)); the time factor is not truncated (r_b = q, as in the timing
+ * experiment).  S and R are never formed: R(S) = (1/n) sum_m conj(X_m) (x) X_m,
+ * so each iteration works on the n^2 Gram blocks X_m X_m'^H.
+ *   X     device complex64 [n][p][q] (snapshot m, channel i, sample k)
+ *   A     device complex64 [p][p], row-major: the final space factor A-hat
+ *   B     device complex64 [q][q], row-major, or NULL: the final time factor
+ *         B-hat = vec^-1(R^T conj(a) / ||a||^2)
+ *   stats device double [4], or NULL: eta, iterations, ||R||_F, ||b||
+ * Limits: 1 <= p <= 8, 2 <= q <= 16384, n >= 1, n * p <= 64, 1 <= r_a <= p.
+ * Allocates nothing; enqueued on hip_stream.
+ * Errors: INVALID_ARG, DEVICE. */
+typedef struct {
+  int32_t n, p, q, r_a;
+  double eps;
+  int32_t min_iter, max_iter;
+} stap_lrk_config;
+
+stap_status stap_lrkron(const stap_lrk_config* cfg, const void* X, float* A, float* B, double* stats,
+                        void* hip_stream);
+
 /* Per-pixel probe: the same computation for a list of pixels, with the
  * intermediate results.  All pointers are device memory:
  *   pix   int32 [npix][2] (r, c)   (pixels outside the valid region get T = 0,
@@ -167,7 +230,9 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
  *   eta   float [npix]              last LR-Kron relative residual
  *   iters int32 [npix]              LR-Kron iterations run
  *   T     float [npix]
- * Any of UA, UB, eta, iters may be NULL.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
+ * Any of UA, UB, eta, iters may be NULL.  Plans with a statistic variant
+ * (classical filter, Doppler bank, several passes) are refused with
+ * UNSUPPORTED.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
 typedef struct {
   float* UA;
   float* UB;
@@ -194,7 +259,9 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
  * this batch signature in this process, else 16.  Results are bitwise equal to
  * stap_run on each tile alone.  The frames and outputs named by the tiles must
  * stay valid while the batch is launched.  Must be called with the device that
- * will run the batch current.
+ * will run the batch current.  Tiles whose plan has a statistic variant
+ * (classical filter, Doppler bank, several passes) are refused with
+ * UNSUPPORTED (those run through stap_run_ex).
  * Errors: INVALID_ARG, UNSUPPORTED, OUT_OF_MEMORY, DEVICE. */
 typedef struct {
   const stap_plan_t* plan;
@@ -254,11 +321,17 @@ stap_status stap_server_create(size_t hbm_budget_bytes, int32_t max_inflight, in
 /* Queues one frame.  x: complex64 [p][H][W][q], host memory (or device memory
  * if x_on_device != 0); T_host: float [H][W] and D_host: uint8 [H][W] (or
  * NULL), host memory written when the frame completes.  x, T_host and D_host
- * must stay valid until stap_server_wait returns for the ticket.  Returns at
- * once with a ticket.  Errors: INVALID_ARG, UNSUPPORTED, BUSY (the frame can
- * never fit in the budget), DEVICE. */
+ * must stay valid until stap_server_wait returns for the ticket.  For a
+ * device-resident x, hip_stream is the stream whose work produces x: the
+ * call records an event on it and the server reads x only after the work
+ * enqueued there before the call (NULL = the default stream); host frames
+ * ignore it and must be complete at the call.  Returns at once with a
+ * ticket.  Plans with a statistic variant are refused with UNSUPPORTED.
+ * Errors: INVALID_ARG, UNSUPPORTED, BUSY (the frame can never fit in the
+ * budget), DEVICE. */
 stap_status stap_server_submit(stap_server_t* server, const stap_plan_t* plan, const void* x, int32_t H, int32_t W,
-                               int32_t x_on_device, float* T_host, uint8_t* D_host, uint64_t* ticket);
+                               int32_t x_on_device, float* T_host, uint8_t* D_host, void* hip_stream,
+                               uint64_t* ticket);
 
 /* Waits until the frame's results are in T_host / D_host (timeout_ms < 0:
  * no limit) and releases the ticket.  latency_s: submit to results in host

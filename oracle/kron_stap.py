@@ -225,7 +225,9 @@ def eig_truncate(M: np.ndarray, r: int):
 # Algorithm 2: LR-Kron (batched over pixels, per-pixel stop rule R6)
 # --------------------------------------------------------------------------
 def lr_kron(R: np.ndarray, p: int, q: int, r_a: int, r_b: int,
-            eps: float = 1e-6, min_iter: int = 2, max_iter: int = 50) -> dict:
+            eps: float = 1e-6, min_iter: int = 2, max_iter: int = 50, truncate_b: bool = True) -> dict:
+    """Algorithm 2 on R [N, p^2, q^2] (or one R).  truncate_b=False skips the
+    final rank-r_b eigendecomposition of B-hat (U_B, lam_B are then None)."""
     R = np.asarray(R, dtype=np.complex128)
     single = R.ndim == 2
     if single:
@@ -272,12 +274,12 @@ def lr_kron(R: np.ndarray, p: int, q: int, r_a: int, r_b: int,
     bfin = _mtv(Rs, np.conj(a)) / np.sum(np.abs(a) ** 2, 1)[:, None]
     Bm = _unvec(bfin, q)
     Bm = (Bm + np.conj(np.swapaxes(Bm, -1, -2))) / 2.0
-    lam_B, U_B, _ = top_eigvecs(Bm, r_b)
+    lam_B, U_B = (top_eigvecs(Bm, r_b)[:2]) if truncate_b else (None, None)
     Am = _unvec(a, p)
     out = dict(A=Am, B=Bm, U_A=U_A, U_B=U_B, eta=eta, iters=iters,
                lam_A=lam_A, lam_B=lam_B, zero=zero)
     if single:
-        out = {k: v[0] for k, v in out.items()}
+        out = {k: (None if v is None else v[0]) for k, v in out.items()}
     return out
 
 

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY",
                 6: "INTERNAL"}
 PRECISIONS = {"fp32": 0, "bf16x3": 1}
 STAT_MODES = {"glrt": 0, "fixed": 1}
+FILTERS = {"kron": 0, "classical": 1}
 
 
 class StapError(RuntimeError):
@@ -43,7 +44,18 @@ class StapConfig(ctypes.Structure):
         ("b_steer", ctypes.POINTER(ctypes.c_float)), ("h_steer", ctypes.POINTER(ctypes.c_float)),
         ("tau", ctypes.c_double), ("pfa", ctypes.c_double),
         ("precision", ctypes.c_int32),
+        ("filter", ctypes.c_int32), ("nbank", ctypes.c_int32), ("passes", ctypes.c_int32),
     ]
+
+
+class StapLrkConfig(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("p", ctypes.c_int32), ("q", ctypes.c_int32), ("r_a", ctypes.c_int32),
+                ("eps", ctypes.c_double), ("min_iter", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
+
+
+class StapOutputs(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_void_p), ("D", ctypes.c_void_p), ("E", ctypes.c_void_p), ("bin", ctypes.c_void_p),
+                ("Tpass", ctypes.c_void_p), ("C", ctypes.c_void_p)]
 
 
 class StapProbeOut(ctypes.Structure):
@@ -80,6 +92,8 @@ def lib() -> ctypes.CDLL:
         "stap_plan_moves": [p_, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i32)],
         "stap_run": [p_, p_, i32, i32, p_, p_, p_],
+        "stap_run_ex": [p_, p_, i32, i32, ctypes.POINTER(StapOutputs), p_],
+        "stap_lrkron": [ctypes.POINTER(StapLrkConfig), p_, p_, p_, p_, p_],
         "stap_probe": [p_, p_, i32, i32, p_, i32, ctypes.POINTER(StapProbeOut), p_],
         "stap_run_batch": [ctypes.POINTER(StapTile), i32, p_],
         "stap_batch_create": [ctypes.POINTER(StapTile), i32, i32, ctypes.POINTER(p_)],
@@ -89,7 +103,7 @@ def lib() -> ctypes.CDLL:
                             ctypes.POINTER(i32)],
         "stap_batch_destroy": [p_],
         "stap_server_create": [ctypes.c_size_t, i32, ctypes.c_int64, ctypes.POINTER(p_)],
-        "stap_server_submit": [p_, p_, p_, i32, i32, i32, p_, p_, ctypes.POINTER(ctypes.c_uint64)],
+        "stap_server_submit": [p_, p_, p_, i32, i32, i32, p_, p_, p_, ctypes.POINTER(ctypes.c_uint64)],
         "stap_server_wait": [p_, ctypes.c_uint64, i32, ctypes.POINTER(ctypes.c_double)],
         "stap_server_stats": [p_, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
@@ -125,7 +139,8 @@ class Plan:
                  stencil: Optional[Sequence] = None, window: int = 0, guard: int = 3,
                  eps: float = 1e-6, min_iter: int = 2, max_iter: int = 50,
                  stat_mode: str = "glrt", b_steer=None, h_steer=None,
-                 tau: float = 0.0, pfa: float = 1e-4, precision: str = "fp32"):
+                 tau: float = 0.0, pfa: float = 1e-4, precision: str = "fp32", filter: str = "kron",
+                 nbank: int = 0, passes: int = 1):
         L = lib()
         cfg = StapConfig()
         _check(L.stap_config_default(ctypes.byref(cfg)))
@@ -136,6 +151,9 @@ class Plan:
         cfg.stat_mode = STAT_MODES[stat_mode]
         cfg.tau, cfg.pfa = tau, pfa
         cfg.precision = PRECISIONS[precision]
+        cfg.filter = FILTERS[filter]
+        cfg.nbank = nbank
+        cfg.passes = passes
         keep = []
         if stencil is not None:
             st = np.ascontiguousarray(np.asarray(stencil, dtype=np.int32).reshape(-1))
@@ -155,6 +173,7 @@ class Plan:
         self._h = handle
         self.p, self.q, self.n, self.r_a, self.r_b = p, q, n, r_a, r_b
         self.precision = precision
+        self.filter, self.nbank, self.passes = filter, nbank, passes
         tau_v = ctypes.c_double()
         ints = [ctypes.c_int32() for _ in range(5)]
         _check(L.stap_plan_info(self._h, ctypes.byref(tau_v), *[ctypes.byref(v) for v in ints]))
@@ -235,6 +254,48 @@ def run(plan: Plan, x, T=None, D=None, stream=None, with_detections: bool = True
     _check(lib().stap_run(plan.handle, ctypes.c_void_p(x.data_ptr()), H, W, ctypes.c_void_p(T.data_ptr()),
                           ctypes.c_void_p(D.data_ptr()) if D is not None else None, _stream_handle(stream)))
     return T, D
+
+
+def run_ex(plan: Plan, x, enhancement: bool = True, bins: bool = True, stream=None) -> dict:
+    """Whole-frame pass with the optional outputs of stap_run_ex: T, D, the
+    enhancement image E, the Doppler bin of the maximum, and for multipass
+    plans the per-pass images T_pass [K, H, W] and change images C [K-1, H, W]."""
+    import torch
+    H, W = _check_frame(plan, x)
+    dev = x.device
+    out = dict(T=torch.empty((H, W), dtype=torch.float32, device=dev),
+               D=torch.empty((H, W), dtype=torch.uint8, device=dev),
+               E=torch.empty((H, W), dtype=torch.float32, device=dev) if enhancement else None,
+               bin=torch.empty((H, W), dtype=torch.uint8, device=dev) if bins else None)
+    if plan.passes > 1:
+        out["T_pass"] = torch.empty((plan.passes, H, W), dtype=torch.float32, device=dev)
+        out["C"] = torch.empty((plan.passes - 1, H, W), dtype=torch.float32, device=dev)
+    ptr = lambda name: out[name].data_ptr() if out.get(name) is not None else None  # noqa: E731
+    so = StapOutputs(ptr("T"), ptr("D"), ptr("E"), ptr("bin"), ptr("T_pass"), ptr("C"))
+    _check(lib().stap_run_ex(plan.handle, ctypes.c_void_p(x.data_ptr()), H, W, ctypes.byref(so),
+                             _stream_handle(stream)))
+    return out
+
+
+def lrkron(X, r_a: int = 1, eps: float = 1e-6, min_iter: int = 2, max_iter: int = 50, with_B: bool = True,
+           stream=None) -> dict:
+    """stap_lrkron: LR-Kron on the covariance of the snapshots X
+    (torch.complex64 [n, p, q] on a GPU).  Returns A [p, p], B [q, q] (or
+    None) and stats (float64: eta, iterations, ||R||_F, ||b||)."""
+    import torch
+    if not isinstance(X, torch.Tensor) or X.dtype != torch.complex64 or not X.is_cuda or X.dim() != 3:
+        raise TypeError("X must be a torch.complex64 tensor [n, p, q] on a GPU")
+    X = X.contiguous()
+    n, p, q = (int(v) for v in X.shape)
+    dev = X.device
+    A = torch.empty((p, p), dtype=torch.complex64, device=dev)
+    B = torch.empty((q, q), dtype=torch.complex64, device=dev) if with_B else None
+    stats = torch.empty(4, dtype=torch.float64, device=dev)
+    cfg = StapLrkConfig(n, p, q, r_a, eps, min_iter, max_iter)
+    _check(lib().stap_lrkron(ctypes.byref(cfg), ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(A.data_ptr()),
+                             ctypes.c_void_p(B.data_ptr()) if B is not None else None,
+                             ctypes.c_void_p(stats.data_ptr()), _stream_handle(stream)))
+    return dict(A=A, B=B, stats=stats, _keep=X)
 
 
 def probe(plan: Plan, x, pix, stream=None) -> dict:
@@ -330,9 +391,12 @@ class Server:
         T = torch.empty((H, W), dtype=torch.float32, pin_memory=True)
         D = torch.empty((H, W), dtype=torch.uint8, pin_memory=True) if with_detections else None
         t = ctypes.c_uint64()
+        # a device frame is read only after the work torch has enqueued for it
+        stream = _stream_handle(None) if x.is_cuda else None
         _check(lib().stap_server_submit(self._h, plan.handle, ctypes.c_void_p(x.data_ptr()), H, W, int(x.is_cuda),
                                         ctypes.c_void_p(T.data_ptr()),
-                                        ctypes.c_void_p(D.data_ptr()) if D is not None else None, ctypes.byref(t)))
+                                        ctypes.c_void_p(D.data_ptr()) if D is not None else None, stream,
+                                        ctypes.byref(t)))
         self._keep[t.value] = (plan, x, T, D)
         return t.value
 

@@ -271,6 +271,9 @@ stap_status stap_config_default(stap_config* cfg) {
   cfg->tau = 0.0;
   cfg->pfa = 1e-4;
   cfg->precision = STAP_PREC_FP32;
+  cfg->filter = STAP_FILTER_KRON;
+  cfg->nbank = 0;
+  cfg->passes = 1;
   return ok();
 }
 
@@ -298,6 +301,13 @@ stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out) {
   if (!(c.tau > 0.0) && !(c.pfa > 0.0 && c.pfa < 1.0))
     return fail(STAP_ERR_INVALID_ARG, "need tau > 0 or 0 < pfa < 1");
   if (!std::isfinite(c.tau)) return fail(STAP_ERR_INVALID_ARG, "tau must be finite");
+  if (c.filter != STAP_FILTER_KRON && c.filter != STAP_FILTER_CLASSICAL)
+    return fail(STAP_ERR_INVALID_ARG, "unknown filter %d", c.filter);
+  if (c.nbank < 0 || c.nbank > 64) return fail(STAP_ERR_INVALID_ARG, "nbank = %d outside [0, 64]", c.nbank);
+  if (c.passes < 1 || c.p % c.passes != 0)
+    return fail(STAP_ERR_INVALID_ARG, "passes = %d must be >= 1 and divide p = %d", c.passes, c.p);
+  if (c.passes > 1 && c.filter != STAP_FILTER_KRON)
+    return fail(STAP_ERR_INVALID_ARG, "several passes are combined with the Kron-STAP filter only");
 
   stap_plan_s* pl = new (std::nothrow) stap_plan_s();
   if (!pl) return fail(STAP_ERR_OUT_OF_MEMORY, "plan allocation failed");
@@ -396,12 +406,15 @@ stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out) {
   pl->cfg.stencil = pl->stencil.data();
   pl->cfg.b_steer = pl->b_steer.data();
   pl->cfg.h_steer = pl->h_steer.empty() ? nullptr : pl->h_steer.data();
+  // null law of T under white noise with exact subspaces: Gamma(p - r_a, 1)
+  // for the Kron-STAP filter, Gamma(p, 1) for the classical one
+  const int dof = (c.filter == STAP_FILTER_CLASSICAL) ? c.p : c.p - c.r_a;
   if (c.tau > 0.0) {
     pl->tau = c.tau;
-  } else if (c.p - c.r_a >= 1) {
-    pl->tau = gamma_isf_int(c.p - c.r_a, c.pfa);
+  } else if (dof >= 1) {
+    pl->tau = gamma_isf_int(dof, c.pfa);
   } else {
-    pl->tau = 0.0;   // r_a == p: F_A = 0 and T is identically 0
+    pl->tau = 0.0;   // Kron-STAP with r_a == p: F_A = 0 and T is identically 0
   }
   if (!kstap::kernel_available(c.p, c.q, c.r_b, c.precision)) {
     delete pl;
@@ -486,16 +499,29 @@ stap_status stap_plan_moves(const stap_plan_t* plan, int32_t move, int32_t* nadd
 
 stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t W, float* T, uint8_t* D,
                      void* hip_stream) {
+  stap_outputs out;
+  std::memset(&out, 0, sizeof(out));
+  out.T = T;
+  out.D = D;
+  return stap_run_ex(plan, x, H, W, &out, hip_stream);
+}
+
+stap_status stap_run_ex(const stap_plan_t* plan, const void* x, int32_t H, int32_t W, const stap_outputs* out,
+                        void* hip_stream) {
   stap_status st = check_frame(plan, x, H, W);
   if (st != STAP_OK) return st;
-  if (!T) return fail(STAP_ERR_INVALID_ARG, "T is NULL");
+  if (!out || !out->T) return fail(STAP_ERR_INVALID_ARG, "out and out->T must not be NULL");
+  if ((out->Tpass || out->C) && plan->cfg.passes < 2)
+    return fail(STAP_ERR_INVALID_ARG, "Tpass and C need a plan with passes > 1");
   kstap::KParams k;
   fill_params(plan, x, H, W, &k);
-  k.T = T;
-  k.D = D;
+  k.T = out->T;
+  k.D = out->D;
+  k.E = out->E;
+  k.bin = out->bin;
+  k.Tpass = out->Tpass;
+  k.C = out->C;
   const int64_t total = kstap::tiled_positions(H, W);
-  // one sliding-window chain per workgroup: runs start on a chain, so the
-  // chains are the same for every decomposition
   const int64_t ppb = (plan->cfg.p * plan->cfg.q > 64) ? kstap::kChainWide : kstap::kChainNarrow;
   k.pix_per_block = int32_t(ppb);
   k.nlogical = int32_t((total + ppb - 1) / ppb);
@@ -510,11 +536,40 @@ stap_status stap_run(const stap_plan_t* plan, const void* x, int32_t H, int32_t 
   return ok();
 }
 
+stap_status stap_lrkron(const stap_lrk_config* cfg, const void* X, float* A, float* B, double* stats,
+                        void* hip_stream) {
+  if (!cfg || !X || !A) return fail(STAP_ERR_INVALID_ARG, "cfg, X and A must not be NULL");
+  const stap_lrk_config& c = *cfg;
+  if (c.p < 1 || c.p > 8) return fail(STAP_ERR_INVALID_ARG, "p = %d outside [1, 8]", c.p);
+  if (c.q < 2 || c.q > 16384) return fail(STAP_ERR_INVALID_ARG, "q = %d outside [2, 16384]", c.q);
+  if (c.n < 1 || c.n * c.p > 64) return fail(STAP_ERR_INVALID_ARG, "need n >= 1 and n * p <= 64 (n = %d)", c.n);
+  if (c.r_a < 1 || c.r_a > c.p) return fail(STAP_ERR_INVALID_ARG, "r_a = %d outside [1, %d]", c.r_a, c.p);
+  if (c.min_iter < 1 || c.max_iter < c.min_iter || c.max_iter > 1000)
+    return fail(STAP_ERR_INVALID_ARG, "need 1 <= min_iter <= max_iter <= 1000 (got %d, %d)", c.min_iter, c.max_iter);
+  if (!std::isfinite(c.eps)) return fail(STAP_ERR_INVALID_ARG, "eps must be finite");
+  kstap::LrkParams k;
+  k.n = c.n;
+  k.p = c.p;
+  k.q = c.q;
+  k.r_a = c.r_a;
+  k.min_iter = c.min_iter;
+  k.max_iter = c.max_iter;
+  k.eps = c.eps;
+  k.A = reinterpret_cast<float2*>(A);
+  k.B = reinterpret_cast<float2*>(B);
+  k.stats = stats;
+  const int e = kstap::launch_lrkron(static_cast<const float2*>(X), k, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "large-q launch: %s", hipGetErrorString(hipError_t(e)));
+  return ok();
+}
+
 stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_t W, const int32_t* pix,
                        int32_t npix, const stap_probe_out* out, void* hip_stream) {
   stap_status st = check_frame(plan, x, H, W);
   if (st != STAP_OK) return st;
   if (!out || !out->T) return fail(STAP_ERR_INVALID_ARG, "out and out->T must not be NULL");
+  if (plan->cfg.filter != STAP_FILTER_KRON || plan->cfg.nbank != 0 || plan->cfg.passes != 1)
+    return fail(STAP_ERR_UNSUPPORTED, "the probe runs the Kron-STAP statistic of one temporal steering");
   if (npix < 0) return fail(STAP_ERR_INVALID_ARG, "npix < 0");
   if (npix == 0) return ok();
   if (!pix) return fail(STAP_ERR_INVALID_ARG, "pix is NULL");
@@ -560,6 +615,11 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
       return fail(STAP_ERR_INVALID_ARG, "tile %d: T is NULL", t);
     }
     const stap_config& c = tl.plan->cfg;
+    if (c.filter != STAP_FILTER_KRON || c.nbank != 0 || c.passes != 1) {
+      batch_free(b);
+      return fail(STAP_ERR_UNSUPPORTED, "tile %d: statistic variants (filter, bank, passes) run through stap_run_ex",
+                  t);
+    }
     const int cls = kstap::kernel_class(c.p, c.q, c.r_b, c.precision);
     if (cls < 0) {
       batch_free(b);

@@ -936,6 +936,25 @@ struct Groups {
 template <bool B, typename T, typename F> struct Pick { using type = T; };
 template <typename T, typename F> struct Pick<false, T, F> { using type = F; };
 
+// True when the plan asks for more than the Kron-STAP statistic of one
+// temporal steering (uniform across the grid).
+__host__ __device__ __forceinline__ bool has_variants(const KParams& prm) {
+  return prm.filter != 0 || prm.nbank != 0 || prm.passes != 1 || prm.E != nullptr || prm.bin != nullptr;
+}
+
+// Run mode: every output of a pixel outside the valid region is zero.
+__device__ __forceinline__ void write_outside(const KParams& prm, int64_t idx) {
+  prm.T[idx] = 0.f;
+  if (prm.D) prm.D[idx] = 0;
+  if (prm.E) prm.E[idx] = 0.f;
+  if (prm.bin) prm.bin[idx] = 0;
+  const int64_t hw = int64_t(prm.H) * prm.W;
+  for (int k = 0; k < prm.passes; ++k) {
+    if (prm.Tpass) prm.Tpass[k * hw + idx] = 0.f;
+    if (prm.C && k > 0) prm.C[(k - 1) * hw + idx] = 0.f;
+  }
+}
+
 // ------------------------------------------------ a6 + a8, batched
 // Top-r_b time subspace, projected test vector and statistic for up to
 // 64 / QP queued pixels of one wavefront: lane group `slot` (QP lanes) serves
@@ -944,7 +963,7 @@ template <typename T, typename F> struct Pick<false, T, F> { using type = F; };
 // index, a flag (0 ok, 1 zero covariance, 2 non-finite), eta, the iteration
 // count and U_A (p x RAM).  Writes T (and D, or the probe outputs).
 // WAVE_LOCAL: other wavefronts of the workgroup run their own tails.
-template <int P, int Q, int RBM, int MODE, typename EC, bool WAVE_LOCAL>
+template <int P, int Q, int RBM, int MODE, typename EC, bool WAVE_LOCAL, bool VAR>
 __device__ __forceinline__ void tail_batch(const KParams& prm, const float2 (&Bq)[Q], int slot, int nfill,
                                            const int* sQflag, const int64_t* sQidx, const float* sQeta,
                                            const int* sQit, const EC (*sQUA)[P * ((P < kMaxRA) ? P : kMaxRA)],
@@ -974,79 +993,167 @@ __device__ __forceinline__ void tail_batch(const KParams& prm, const float2 (&Bq
     pc = prm.pix[2 * pidx + 1];
   }
   const bool use = rok && flag == 0;
-  const EC bsk = use ? cto<EC>(prm.b_s[tk]) : czero<EC>();
-  EC gk = bsk;
-  if (r_b > 0) {
-#pragma unroll
-    for (int c = 0; c < RBM; ++c) {
-      if (c >= r_b) continue;
-      const EC coef = gsum<QP>(ccfma(vb[c], bsk, czero<EC>()));
-      if (use) gk = csub(gk, cmul(vb[c], coef));
-    }
-  }
+  // this lane's sample of every channel of the test snapshot
   const float2* xt = prm.x + (int64_t(pr) * W + pc) * Q;
-  EC w[P];
+  EC xv[P];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const EC xv = use ? cto<EC>(xt[int64_t(i) * H * W * Q + tk]) : czero<EC>();
-    w[i] = gsum<QP>(cmul(xv, cconj(gk)));
-  }
-  const ES den = gsum<QP>(ES(bsk.x * gk.x + bsk.y * gk.y));
+  for (int i = 0; i < P; ++i) xv[i] = use ? cto<EC>(xt[int64_t(i) * H * W * Q + tk]) : czero<EC>();
   const EC* Uq = sQUA[slot_ok ? slot : 0];   // U_A of the queued pixel, p x RAM
-  EC z[P];
-  {
-    EC cw[RAM];
-#pragma unroll
-    for (int c = 0; c < RAM; ++c) {
-      cw[c] = czero<EC>();
-      if (c < r_a) {
-#pragma unroll
-        for (int i = 0; i < P; ++i) cw[c] = ccfma(Uq[i * RAM + c], w[i], cw[c]);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < P; ++i) {
-      z[i] = w[i];
-#pragma unroll
-      for (int c = 0; c < RAM; ++c)
-        if (c < r_a) z[i] = csub(z[i], cmul(Uq[i * RAM + c], cw[c]));
-    }
-  }
-  const bool den_ok = den > ES(1e-12) * ES(prm.bs_norm2);
-  float T;
-  if (prm.stat_mode == 0) {
-    ES num = 0;
-#pragma unroll
-    for (int i = 0; i < P; ++i) num += cabs2(z[i]);
-    T = den_ok ? float(num / den) : 0.f;
-  } else {
-    EC hz = czero<EC>(), fh[P], hs[P];
-#pragma unroll
-    for (int i = 0; i < P; ++i) fh[i] = hs[i] = cto<EC>(prm.h_s[i]);
+  // z <- (I - U_A U_A^H) z
+  auto project_a = [&](EC (&z)[P]) __attribute__((always_inline)) {
 #pragma unroll
     for (int c = 0; c < RAM; ++c) {
       if (c >= r_a) continue;
-      EC ch = czero<EC>();
+      EC cw = czero<EC>();
 #pragma unroll
-      for (int i = 0; i < P; ++i) ch = ccfma(Uq[i * RAM + c], hs[i], ch);
+      for (int i = 0; i < P; ++i) cw = ccfma(Uq[i * RAM + c], z[i], cw);
 #pragma unroll
-      for (int i = 0; i < P; ++i) fh[i] = csub(fh[i], cmul(Uq[i * RAM + c], ch));
+      for (int i = 0; i < P; ++i) z[i] = csub(z[i], cmul(Uq[i * RAM + c], cw));
     }
-    ES hfh = 0;
+  };
+  // fixed spatial steering: h and F_A h
+  EC hs[P], fh[P];
+  ES hfa = 0, hpa = 0;   // ||F_A h||^2, ||P_A h||^2
+  if (prm.stat_mode != 0) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) fh[i] = hs[i] = cto<EC>(prm.h_s[i]);
+    project_a(fh);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      hz = ccfma(hs[i], z[i], hz);
-      hfh += hs[i].x * fh[i].x + hs[i].y * fh[i].y;
+      hfa += hs[i].x * fh[i].x + hs[i].y * fh[i].y;
+      const EC ph = csub(hs[i], fh[i]);
+      hpa += cabs2(ph);
     }
-    const bool ok = den_ok && hfh > ES(1e-12) * ES(prm.h_norm2);
-    T = ok ? float(cabs2(hz) / (hfh * den)) : 0.f;
+  }
+  // Temporal steering: the plan's b_s, or each bin of a Doppler bank
+  // b_m[k] = exp(2 pi j ((m k) mod M) / M); the statistic is the largest over
+  // the bank, the bin its first maximiser.
+  const int nbank = VAR ? prm.nbank : 0;
+  const int nbins = nbank > 0 ? nbank : 1;
+  const int K = VAR ? prm.passes : 1, PP = K > 1 ? P / K : P;
+  const int filter = VAR ? prm.filter : 0;
+  float* const Eout = VAR ? prm.E : nullptr;
+  float T = 0.f, Ebest = 0.f;
+  int best = 0;
+  ES ez[P];   // per-channel energy |z_i|^2 / (b^H F_B b) at the best bin (passes > 1)
+#pragma unroll
+  for (int i = 0; i < P; ++i) ez[i] = 0;
+  for (int m = 0; m < nbins; ++m) {
+    EC bsk;
+    ES bn2;
+    if (nbank > 0) {
+      const int ph = (m * tk) % nbank;
+      float sn, cs;
+      sincospif(float(2 * ph) / float(nbank), &sn, &cs);
+      bsk = use ? cto<EC>(make_float2(cs, sn)) : czero<EC>();
+      bn2 = ES(Q);
+    } else {
+      bsk = use ? cto<EC>(prm.b_s[tk]) : czero<EC>();
+      bn2 = ES(prm.bs_norm2);
+    }
+    // g = F_B b
+    EC gk = bsk;
+    if (r_b > 0) {
+#pragma unroll
+      for (int c = 0; c < RBM; ++c) {
+        if (c >= r_b) continue;
+        const EC coef = gsum<QP>(ccfma(vb[c], bsk, czero<EC>()));
+        if (use) gk = csub(gk, cmul(vb[c], coef));
+      }
+    }
+    // w = X conj(g), z = F_A w
+    EC w[P], z[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) z[i] = w[i] = gsum<QP>(cmul(xv[i], cconj(gk)));
+    const ES den = gsum<QP>(ES(bsk.x * gk.x + bsk.y * gk.y));   // b^H F_B b
+    project_a(z);
+    const bool den_ok = den > ES(1e-12) * bn2;
+    // w0 = X conj(b) (the classical filter, and channel 0's SAR image)
+    EC w0[P];
+    const int nw0 = filter == 1 ? P : (Eout ? 1 : 0);
+#pragma unroll
+    for (int i = 0; i < P; ++i) w0[i] = (i < nw0) ? gsum<QP>(cmul(xv[i], cconj(bsk))) : czero<EC>();
+    ES t;
+    if (filter == 0) {
+      // Kron-STAP, Eq. (25): ||F_A X conj(F_B b)||^2 / (b^H F_B b)
+      if (prm.stat_mode == 0) {
+        ES num = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) num += cabs2(z[i]);
+        t = den_ok ? num / den : ES(0);
+      } else {
+        EC hz = czero<EC>();
+#pragma unroll
+        for (int i = 0; i < P; ++i) hz = ccfma(hs[i], z[i], hz);
+        const bool ok = den_ok && hfa > ES(1e-12) * ES(prm.h_norm2);
+        t = ok ? cabs2(hz) / (hfa * den) : ES(0);
+      }
+    } else {
+      // classical, Eq. (24): the GLRT over h reduces to
+      // ||F_A X b*||^2 / ||b||^2 + ||P_A X conj(F_B b)||^2 / (b^H F_B b)
+      EC z0[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) z0[i] = w0[i];
+      project_a(z0);
+      if (prm.stat_mode == 0) {
+        ES n0 = 0, n1 = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          n0 += cabs2(z0[i]);
+          n1 += cabs2(csub(w[i], z[i]));
+        }
+        t = n0 / bn2 + (den_ok ? n1 / den : ES(0));
+      } else {
+        // u = F_A X b* + P_A X conj(F_B b); h^H G h = ||F_A h||^2 ||b||^2 + ||P_A h||^2 b^H F_B b
+        EC hu = czero<EC>();
+#pragma unroll
+        for (int i = 0; i < P; ++i) hu = ccfma(hs[i], cadd(z0[i], csub(w[i], z[i])), hu);
+        const ES hgh = hfa * bn2 + hpa * (den_ok ? den : ES(0));
+        t = hgh > ES(1e-12) * ES(prm.h_norm2) * bn2 ? cabs2(hu) / hgh : ES(0);
+      }
+    }
+    if (m == 0 || float(t) > T) {
+      T = float(t);
+      best = m;
+      if (Eout) {
+        const ES isar = cabs2(w0[0]) / bn2;   // channel 0's matched-filter intensity
+        Ebest = isar > ES(0) ? float(t / isar) : 0.f;
+      }
+      if (K > 1) {
+#pragma unroll
+        for (int i = 0; i < P; ++i) ez[i] = den_ok ? cabs2(z[i]) / den : ES(0);
+      }
+    }
   }
   if (!isfinite(T)) T = NAN;
   if (flag == 1) T = 0.f;
   if (flag == 2) T = NAN;
   if (slot_ok && tk == 0) {
     prm.T[pidx] = T;
-    if (MODE == kModeRun && prm.D) prm.D[pidx] = (T > prm.tau) ? 1 : 0;
+    if (MODE == kModeRun) {
+      if (prm.D) prm.D[pidx] = (T > prm.tau) ? 1 : 0;
+      const int64_t hw = int64_t(H) * W;
+      if (Eout) Eout[pidx] = flag == 2 ? NAN : (flag == 1 ? 0.f : Ebest);
+      if (VAR && prm.bin) prm.bin[pidx] = uint8_t(flag == 0 ? best : 0);
+      // pass k's image: the energy of its channels of z (passes > 1)
+      if (K > 1 && (prm.Tpass || prm.C)) {
+        ES t0 = 0;
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          if (i < PP) t0 += ez[i];
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          if (k >= K) continue;
+          ES ts = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+            if (i / PP == k) ts += ez[i];
+          if (prm.Tpass) prm.Tpass[k * hw + pidx] = flag == 2 ? NAN : (flag == 1 ? 0.f : float(ts));
+          if (prm.C && k > 0)
+            prm.C[(k - 1) * hw + pidx] = flag == 2 ? NAN : (flag == 1 ? 0.f : float(sqrt(ts) - sqrt(t0)));
+        }
+      }
+    }
     if (MODE == kModeProbe) {
       if (prm.eta) prm.eta[pidx] = sQeta[slot];
       if (prm.iters) prm.iters[pidx] = sQit[slot];
@@ -1101,7 +1208,7 @@ struct Lds {
 // The whole per-pixel pass for `count` pixels starting at `first`: positions
 // in the tiled order of the frame (run mode) or in the pixel list (probe
 // mode).  One 64-lane workgroup; `lds` holds Lds<...>::bytes.
-template <int P, int Q, int RBM, int MODE, int PREC>
+template <int P, int Q, int RBM, int MODE, int PREC, bool VAR = false>
 __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, int64_t count, char* lds) {
   using EC = typename Pick<PREC == 1, double2, float2>::type;   // eigensolver / statistic precision
   using ES = decltype(EC{}.x);
@@ -1177,8 +1284,8 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 
   // ------------------------------------------------ a6 + a8 for G pixels
   auto tail = [&](int nfill) __attribute__((always_inline)) {
-    tail_batch<P, Q, RBM, MODE, EC, false>(prm, Bq, tg, nfill, sQflag, sQidx, sQeta, sQit, sQUA, tail_scratch,
-                                           PREC ? 1e-10 : 2e-6);
+    tail_batch<P, Q, RBM, MODE, EC, false, VAR>(prm, Bq, tg, nfill, sQflag, sQidx, sQeta, sQit, sQUA, tail_scratch,
+                                                PREC ? 1e-10 : 2e-6);
   };
 
   // Sliding window (run mode, FP32 path): every position of a chain but the
@@ -1204,8 +1311,8 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     const bool valid = r >= prm.r0 && r < prm.r1 && c >= prm.c0 && c < prm.c1;
     if (!valid) {
       if (lane == 0) {
-        prm.T[idx] = 0.f;
-        if (MODE == kModeRun && prm.D) prm.D[idx] = 0;
+        if (MODE == kModeRun) write_outside(prm, idx);
+        else prm.T[idx] = 0.f;
         if (MODE == kModeProbe) {
           if (prm.eta) prm.eta[idx] = 0.f;
           if (prm.iters) prm.iters[idx] = 0;
@@ -1543,7 +1650,10 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 
 // Whole frame (run mode) or pixel list (probe mode).  Run mode: workgroup ids
 // are remapped so each of the 8 XCDs takes a contiguous share of the frame.
-template <int P, int Q, int RBM, int MODE, int PREC>
+// VAR: the statistic variants (filter, Doppler bank, enhancement, passes) are
+// compiled into a kernel of their own, so that the plain statistic keeps its
+// register budget.
+template <int P, int Q, int RBM, int MODE, int PREC, bool VAR = false>
 __global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
   __shared__ __attribute__((aligned(16))) char lds[Lds<P, Q, RBM, PREC>::bytes];
   int64_t first, count;
@@ -1560,7 +1670,7 @@ __global__ __launch_bounds__(64, 2) void kstap_kernel(const KParams prm) {
     count = prm.npix - first;
     if (count > prm.pix_per_block) count = prm.pix_per_block;
   }
-  run_pixels<P, Q, RBM, MODE, PREC>(prm, first, count, lds);
+  run_pixels<P, Q, RBM, MODE, PREC, VAR>(prm, first, count, lds);
 }
 
 // Persistent batched kernel: every workgroup pops work items (runs of `ppb`
@@ -1673,7 +1783,7 @@ __device__ __forceinline__ double block_sumd(double v, double* red) {
   return v;
 }
 
-template <int P, int Q, int RBM, int MODE, int PREC>
+template <int P, int Q, int RBM, int MODE, int PREC, bool VAR = false>
 __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t first, int64_t count, char* lds) {
   using EC = typename Pick<PREC == 1, double2, float2>::type;
   using ES = decltype(EC{}.x);
@@ -1769,9 +1879,9 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     float2 Bq[Q];
 #pragma unroll
     for (int l = 0; l < Q; ++l) Bq[l] = own ? cconj(sHq[(slot < nfill ? slot : 0) * QQ + l * Q + tk]) : cz();
-    tail_batch<P, Q, RBM, MODE, EC, true>(prm, Bq, slot, nfill, sQflag, sQidx, sQeta, sQit, sQUA,
-                                          reinterpret_cast<EC*>(stage) + wave * (RBM * Q * G),
-                                          PREC ? 1e-10 : 2e-6);
+    EC* const scr = reinterpret_cast<EC*>(stage) + wave * (RBM * Q * G);
+    tail_batch<P, Q, RBM, MODE, EC, true, VAR>(prm, Bq, slot, nfill, sQflag, sQidx, sQeta, sQit, sQUA, scr,
+                                               PREC ? 1e-10 : 2e-6);
     block_sync();
   };
 
@@ -1793,8 +1903,8 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     const bool valid = r >= prm.r0 && r < prm.r1 && c >= prm.c0 && c < prm.c1;
     if (!valid) {
       if (tid == 0) {
-        prm.T[idx] = 0.f;
-        if (MODE == kModeRun && prm.D) prm.D[idx] = 0;
+        if (MODE == kModeRun) write_outside(prm, idx);
+        else prm.T[idx] = 0.f;
         if (MODE == kModeProbe) {
           if (prm.eta) prm.eta[idx] = 0.f;
           if (prm.iters) prm.iters[idx] = 0;
@@ -2252,7 +2362,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
   }
 }
 
-template <int P, int Q, int RBM, int MODE, int PREC>
+template <int P, int Q, int RBM, int MODE, int PREC, bool VAR = false>
 __global__ __launch_bounds__(256, 1) void kstap_wide_kernel(const KParams prm) {
   __shared__ __attribute__((aligned(16))) char lds[WideLds<P, Q, RBM, PREC>::bytes];
   int64_t first, count;
@@ -2269,7 +2379,7 @@ __global__ __launch_bounds__(256, 1) void kstap_wide_kernel(const KParams prm) {
     count = prm.npix - first;
     if (count > prm.pix_per_block) count = prm.pix_per_block;
   }
-  run_pixels_wide<P, Q, RBM, MODE, PREC>(prm, first, count, lds);
+  run_pixels_wide<P, Q, RBM, MODE, PREC, VAR>(prm, first, count, lds);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -2279,7 +2389,10 @@ int launch_one(int mode, const KParams& prm, hipStream_t stream) {
   if (units <= 0) return hipSuccess;
   int64_t grid = (mode == kModeRun) ? ((units + 7) / 8) * 8 : units;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  if (mode == kModeRun)
+  if (mode == kModeRun && has_variants(prm))
+    hipLaunchKernelGGL((kstap_kernel<P, Q, RBM, kModeRun, PREC, true>), dim3(unsigned(grid)), dim3(64), 0, stream,
+                       prm);
+  else if (mode == kModeRun)
     hipLaunchKernelGGL((kstap_kernel<P, Q, RBM, kModeRun, PREC>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
   else
     hipLaunchKernelGGL((kstap_kernel<P, Q, RBM, kModeProbe, PREC>), dim3(unsigned(grid)), dim3(64), 0, stream, prm);
@@ -2292,7 +2405,10 @@ int launch_wide(int mode, const KParams& prm, hipStream_t stream) {
   if (units <= 0) return hipSuccess;
   int64_t grid = (mode == kModeRun) ? ((units + 7) / 8) * 8 : units;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  if (mode == kModeRun)
+  if (mode == kModeRun && has_variants(prm))
+    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeRun, PREC, true>), dim3(unsigned(grid)), dim3(256), 0,
+                       stream, prm);
+  else if (mode == kModeRun)
     hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeRun, PREC>), dim3(unsigned(grid)), dim3(256), 0, stream, prm);
   else
     hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeProbe, PREC>), dim3(unsigned(grid)), dim3(256), 0, stream,

@@ -140,6 +140,9 @@ stap_status fill_params(const stap_plan_s* pl, const void* x, int H, int W, ksta
   k->min_iter = c.min_iter;
   k->max_iter = c.max_iter;
   k->stat_mode = c.stat_mode;
+  k->filter = c.filter;
+  k->nbank = c.nbank;
+  k->passes = c.passes;
   k->eps = c.eps;
   k->tau = float(pl->tau);
   float bn = 0.f, hn = 0.f;

@@ -43,6 +43,14 @@ struct KParams {
   float2* UB;             // [npix][q][r_b]
   float* eta;             // [npix]
   int32_t* iters;         // [npix]
+  // statistic variants (run mode outputs beyond T and D)
+  int32_t filter;         // 0: Kron-STAP projector (Sec. 5, Eq. (25)); 1: classical joint projector (Eq. (24))
+  int32_t nbank;          // 0: the temporal steering b_s; M > 0: the M-bin Doppler bank (Sec. 6.3)
+  int32_t passes;         // K registered passes stacked in the p channels (Sec. 3), >= 1
+  float* E;               // enhancement image [H][W] or null (Sec. 6.3)
+  uint8_t* bin;           // bank bin of the maximum [H][W] or null
+  float* Tpass;           // per-pass images [K][H][W] or null (passes > 1)
+  float* C;               // change images against pass 0 [K-1][H][W] or null (passes > 1; Sec. 6.4)
   float2 b_s[kMaxQ];
   float2 h_s[kMaxP];
   int16_t st[2 * kMaxN];  // stencil (dr, dc)
@@ -56,6 +64,19 @@ struct KParams {
 };
 
 static_assert(sizeof(KParams) <= 4096, "KParams is passed as a kernel argument");
+
+// LR-Kron on one large covariance given by its n training snapshots
+// (stap_lrkron): snapshots X[n][p][q], outputs A[p][p], B[q][q] (or null),
+// stats[4] = eta, iterations, ||R||_F, ||b|| (or null).
+struct LrkParams {
+  int32_t n, p, q, r_a;
+  int32_t min_iter, max_iter;
+  double eps;
+  float2* A;
+  float2* B;
+  double* stats;
+};
+int launch_lrkron(const float2* X, const LrkParams& prm, hipStream_t stream);
 
 enum Mode { kModeRun = 0, kModeProbe = 1 };
 enum Move { kMoveRight = 0, kMoveLeft = 1, kMoveDown = 2 };

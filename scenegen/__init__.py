@@ -260,3 +260,102 @@ def serving_trace(seed: int = BASE_SEED + 4, nframes: int = 300):
         nt = max(1, int(round(side * side * 200 / 2048 ** 2)))
         out.append((SceneSpec(p=3, q=q, H=side, W=side, r_a=1, r_b=3, n_targets=nt, snr_db=(0.0, 15.0)), n))
     return out
+
+
+# ---------------------------------------------------------------- multipass
+@dataclasses.dataclass(frozen=True)
+class MultipassSpec:
+    """K registered passes over one scene (Sec. 3): every pass sees the same
+    time factor B, its own rank-one space factor u_k u_k^H, and clutter
+    coefficients that correlate across passes with `coherence`."""
+    passes: int
+    p: int                           # channels per pass
+    q: int
+    H: int
+    W: int
+    r_b: int = 3
+    coherence: float = 0.9           # correlation of the clutter coefficient between any two passes
+    cnr_db: float = 30.0
+    snr_db: Union[float, Tuple[float, float]] = (5.0, 15.0)
+    n_targets: int = 4               # movers per pass, at independent positions
+
+
+@dataclasses.dataclass
+class MultipassScene:
+    spec: MultipassSpec
+    seed: int
+    x: np.ndarray                    # complex64 [K*p][H][W][q], pass k in channels k*p .. k*p + p - 1
+    targets: np.ndarray              # int64 [K * n_targets, 3] (pass, row, col)
+    U_tilde: np.ndarray              # [K*p, K] orthonormal: pass k's spatial factor in block k of column k
+    A_tilde: np.ndarray              # [K*p, K*p]
+    B: np.ndarray                    # [q, q]
+
+
+def multipass_factors(spec: MultipassSpec, rng: np.random.Generator):
+    """(A_tilde, B, U_tilde) of the K-pass clutter model: A_tilde =
+    U_tilde Cc U_tilde^H with U_tilde = blockdiag(u_1, ..., u_K) and
+    Cc = coherence * 1 1^T + (1 - coherence) I, B of rank r_b; scaled so that
+    tr(A_tilde (x) B) / (K p q) = 10^(CNR/10)."""
+    K, p, q = spec.passes, spec.p, spec.q
+    U = np.zeros((K * p, K), dtype=np.complex128)
+    for k in range(K):
+        U[k * p:(k + 1) * p, k] = _unitary_q(rng, p, 1)[:, 0]
+    Cc = spec.coherence * np.ones((K, K)) + (1.0 - spec.coherence) * np.eye(K)
+    A = U @ Cc @ U.conj().T
+    ub = _unitary_q(rng, q, spec.r_b)
+    lb = rng.uniform(0.5, 1.0, spec.r_b)
+    B = (ub * lb) @ ub.conj().T
+    B *= 10.0 ** (spec.cnr_db / 10.0) * K * p * q / (np.real(np.trace(A)) * np.real(np.trace(B)))
+    return A, B, U
+
+
+def make_multipass_scene(spec: MultipassSpec, seed: int = BASE_SEED) -> MultipassScene:
+    """Draw one stacked K-pass frame: per pixel CN(0, A_tilde (x) B + I), then
+    movers in single passes (Eq. (8) on that pass's channels)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    K, p, q, H, W = spec.passes, spec.p, spec.q, spec.H, spec.W
+    P = K * p
+    A, B, U = multipass_factors(spec, rng)
+    cov = np.kron(A, B) + np.eye(P * q)
+    lam, v = np.linalg.eigh(cov)
+    root = (v * np.sqrt(np.clip(lam, 0.0, None))) @ v.conj().T
+    npx = H * W
+    w = np.empty((npx, P * q), dtype=np.complex64)
+    w.real = rng.standard_normal((npx, P * q), dtype=np.float32)
+    w.imag = rng.standard_normal((npx, P * q), dtype=np.float32)
+    w *= np.float32(1.0 / np.sqrt(2.0))
+    snap = (w @ root.T.astype(np.complex64)).reshape(H, W, P, q)
+    x = np.ascontiguousarray(snap.transpose(2, 0, 1, 3))
+    nt = spec.n_targets
+    tg = []
+    for k in range(K):
+        rows = rng.integers(0, H, nt)
+        cols = rng.integers(0, W, nt)
+        snr = rng.uniform(*spec.snr_db, nt) if isinstance(spec.snr_db, tuple) else np.full(nt, float(spec.snr_db))
+        theta = rng.uniform(0.0, 2.0 * np.pi, nt)
+        phase = rng.uniform(0.0, 2.0 * np.pi, nt)
+        for t in range(nt):
+            alpha = np.sqrt(10.0 ** (snr[t] / 10.0)) * np.exp(1j * phase[t])
+            av = np.exp(1j * theta[t] * np.arange(p))
+            x[k * p:(k + 1) * p, rows[t], cols[t], :] += (alpha * np.outer(av, np.ones(q))).astype(np.complex64)
+            tg.append((k, rows[t], cols[t]))
+    return MultipassScene(spec=spec, seed=seed, x=x, targets=np.array(tg, dtype=np.int64).reshape(-1, 3),
+                          U_tilde=U, A_tilde=A, B=B)
+
+
+# ------------------------------------------------- one large covariance
+def large_q_snapshots(p: int, q: int, n: int, r_a: int = 1, cnr_db: float = 30.0,
+                      seed: int = BASE_SEED) -> np.ndarray:
+    """Training snapshots of the paper's timing workload (Sec. 6.1): a random
+    complex rank-r_a space factor A, the identity time factor B = I_q, n
+    snapshots X_m (p x q) drawn from CN(0, A (x) I_q + I) with tr(A)/p =
+    10^(CNR/10).  Returns complex64 [n, p, q]."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ua = _unitary_q(rng, p, r_a)
+    la = rng.uniform(0.5, 1.0, r_a)
+    la *= 10.0 ** (cnr_db / 10.0) * p / la.sum()
+    root_a = ua * np.sqrt(la)                       # A = root_a root_a^H
+    w = (rng.standard_normal((n, r_a, q)) + 1j * rng.standard_normal((n, r_a, q))) / np.sqrt(2.0)
+    noise = (rng.standard_normal((n, p, q)) + 1j * rng.standard_normal((n, p, q))) / np.sqrt(2.0)
+    X = np.matmul(root_a[None], w) + noise          # rows of A^(1/2) W have covariance A (x) I
+    return X.astype(np.complex64)

@@ -93,7 +93,7 @@ def test_server_rejects_bad_arguments_without_a_device():
     assert L.stap_server_create(1 << 30, 4, -1, ctypes.byref(h)) == 1
     assert L.stap_server_create(1 << 30, 4, 0, None) == 1
     t = ctypes.c_uint64()
-    assert L.stap_server_submit(None, None, None, 8, 8, 0, None, None, ctypes.byref(t)) == 1
+    assert L.stap_server_submit(None, None, None, 8, 8, 0, None, None, None, ctypes.byref(t)) == 1
     assert L.stap_server_wait(None, 1, 0, None) == 1
     assert L.stap_server_stats(None, None, None, None, None) == 1
     assert L.stap_server_destroy(None) == 0

@@ -64,3 +64,28 @@ def test_server_budget_admission():
     for x, (T, D, _) in zip(xs, outs):
         assert torch.equal(T, kstap.run(pl, x.cuda())[0].cpu())
     srv.close()
+
+
+def test_server_device_frame_waits_for_its_producer():
+    """A device frame still being written on torch's stream when it is
+    submitted: the server orders its first read after that work (an event
+    recorded on the producer's stream at submit)."""
+    import paper_1604_03622_amd as kstap
+    pl = kstap.Plan(p=3, q=8, n=64, r_a=1, r_b=3)
+    sc = scenegen.make_scene(scenegen.SceneSpec(p=3, q=8, H=200, W=180, n_targets=3), 451)
+    src = torch.from_numpy(sc.x).cuda()
+    ref, _ = kstap.run(pl, src)
+    torch.cuda.synchronize()
+    srv = kstap.Server(hbm_budget_bytes=1 << 30, max_inflight=4, step_pixels=1 << 16)
+    for trial in range(3):
+        print(f"server: device frame written behind a long producer, trial {trial}", flush=True)
+        a = torch.randn((4096, 4096), device="cuda")
+        y = torch.zeros_like(src)
+        for _ in range(4):
+            a = a @ a
+            a /= a.norm()
+        y.copy_(src)   # enqueued behind the products on torch's stream
+        t = srv.submit(pl, y)
+        T, D, _ = srv.wait(t, timeout_ms=60000)
+        assert torch.equal(T, ref.cpu())
+    srv.close()
