@@ -468,6 +468,8 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--only-form", choices=("large_q", "variants"),
+                    help="run one secondary form alone and print its JSON (for kernel profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -475,6 +477,21 @@ def main():
               "one per GPU, each with the stencil's halo rows)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.only_form:
+        import torch
+        import paper_1604_03622_amd as kstap
+        if args.only_form == "large_q":
+            out = form_large_q(kstap, torch, cpu=False)
+        else:
+            out = form_variants(kstap, torch)
+        if args.calibrate_copy:
+            src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+            dst = src.clone()
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps({"form": args.only_form, "result": out}), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     spec, plan_kw = wl["spec"], wl["plan"]

@@ -255,8 +255,9 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
  * builds one HIP graph: a counter-reset kernel node followed, as parallel
  * branches, by one persistent kernel node per kernel class present; every
  * workgroup of a persistent kernel pops work items from a device counter until
- * the queue is empty.  pix_per_item = 0 takes the autotuned value cached for
- * this batch signature in this process, else 16.  Results are bitwise equal to
+ * the queue is empty.  pix_per_item = 0 takes, per kernel class, the tuned
+ * entry of the tuning cache for the current device (else 16 positions and a
+ * grid of compute units x 8); pix_per_item > 0 applies to every class.  Results are bitwise equal to
  * stap_run on each tile alone.  The frames and outputs named by the tiles must
  * stay valid while the batch is launched.  Must be called with the device that
  * will run the batch current.  Tiles whose plan has a statistic variant
@@ -278,17 +279,45 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
 /* One hipGraphLaunch of the captured graph on hip_stream (asynchronous). */
 stap_status stap_batch_launch(stap_batch_t* batch, void* hip_stream);
 
-/* Autotuner: times the batch (synchronously, on hip_stream, with direct
- * launches) for work-item sizes {4, 8, 16, 32} pixels and persistent grids of
- * {1, 2} x (compute units x 8) workgroups, keeps the fastest (rebuilds the
- * graph once), and records it
- * for this batch signature (kernel classes present and total pixels) in a
- * process-wide cache.  best_ppb / best_grid_mult / best_ms may be NULL. */
+/* Autotuner: for every kernel class of the batch, alone, times (synchronously,
+ * on hip_stream, with direct launches) work items of {16, 32, 64, 128}
+ * positions and persistent grids of {1, 2, 4} x (compute units x 8)
+ * workgroups, keeps each class's fastest, rebuilds the graph, and records the
+ * choices in the tuning cache (stap_tune_record) keyed by (device
+ * architecture, p, q, r_b bound, precision).  best_ppb / best_grid_mult
+ * report the slowest class's choice, best_ms the sum of the classes' times;
+ * any may be NULL. */
 stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best_ppb, int32_t* best_grid_mult,
                             double* best_ms);
 
-/* Batch facts: total pixels, kernel classes present, work-item size, grid
- * multiplier.  Any output pointer may be NULL. */
+/* Kernel class `cls` (0 .. classes-1) of a batch: its p, q, r_b bound (4 or
+ * 8), precision, work-item size and grid multiplier.  Any output may be NULL.
+ * Errors: INVALID_ARG. */
+stap_status stap_batch_class_info(const stap_batch_t* batch, int32_t cls, int32_t* p, int32_t* q,
+                                  int32_t* rb_bound, int32_t* precision, int32_t* pix_per_item,
+                                  int32_t* grid_mult);
+
+/* The tuning cache (host only).  Entries are keyed by (architecture, p, q,
+ * r_b bound, precision), with r_b mapped to its bound (<= 4 -> 4, else 8).
+ * When the environment variable KSTAP_TUNE_CACHE names a file, the cache is
+ * read from it (again whenever it changes) and every recorded entry rewrites
+ * it (JSON, written to a temporary file and renamed), so tuned choices carry
+ * over to later processes; stap_batch_create with pix_per_item = 0 takes each
+ * class's entry for the current device.  arch = NULL means the current
+ * device's architecture (e.g. "gfx950").
+ * stap_tune_lookup: *found = 1 and the entry, or *found = 0 and the defaults
+ *   (16, 1).  Errors: INVALID_ARG (found is NULL).
+ * stap_tune_record: pix_per_item a multiple of 16 in [16, 4096], grid_mult
+ *   in [1, 64]; ms is informative.  Errors: INVALID_ARG (also: the file
+ *   cannot be written). */
+stap_status stap_tune_lookup(const char* arch, int32_t p, int32_t q, int32_t r_b, int32_t precision,
+                             int32_t* pix_per_item, int32_t* grid_mult, int32_t* found);
+stap_status stap_tune_record(const char* arch, int32_t p, int32_t q, int32_t r_b, int32_t precision,
+                             int32_t pix_per_item, int32_t grid_mult, double ms);
+
+/* Batch facts: total pixels, kernel classes present, and the first class's
+ * work-item size and grid multiplier (every class's: stap_batch_class_info).
+ * Any output pointer may be NULL. */
 stap_status stap_batch_info(const stap_batch_t* batch, int64_t* pixels, int32_t* classes, int32_t* pix_per_item,
                             int32_t* grid_mult);
 

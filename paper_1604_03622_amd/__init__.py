@@ -102,6 +102,10 @@ def lib() -> ctypes.CDLL:
         "stap_batch_info": [p_, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i32)],
         "stap_batch_destroy": [p_],
+        "stap_batch_class_info": [p_, i32] + [ctypes.POINTER(i32)] * 6,
+        "stap_tune_lookup": [ctypes.c_char_p, i32, i32, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                             ctypes.POINTER(i32)],
+        "stap_tune_record": [ctypes.c_char_p, i32, i32, i32, i32, i32, i32, ctypes.c_double],
         "stap_server_create": [ctypes.c_size_t, i32, ctypes.c_int64, ctypes.POINTER(p_)],
         "stap_server_submit": [p_, p_, p_, i32, i32, i32, p_, p_, p_, ctypes.POINTER(ctypes.c_uint64)],
         "stap_server_wait": [p_, ctypes.c_uint64, i32, ctypes.POINTER(ctypes.c_double)],
@@ -359,7 +363,12 @@ class Batch:
         px, cl, ppb, mult = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _check(lib().stap_batch_info(self._h, ctypes.byref(px), ctypes.byref(cl), ctypes.byref(ppb),
                                      ctypes.byref(mult)))
-        return dict(pixels=px.value, classes=cl.value, pix_per_item=ppb.value, grid_mult=mult.value)
+        per = []
+        for i in range(cl.value):
+            v = [ctypes.c_int32() for _ in range(6)]
+            _check(lib().stap_batch_class_info(self._h, i, *[ctypes.byref(x) for x in v]))
+            per.append(dict(zip(("p", "q", "rb_bound", "precision", "pix_per_item", "grid_mult"), (x.value for x in v))))
+        return dict(pixels=px.value, classes=cl.value, pix_per_item=ppb.value, grid_mult=mult.value, per_class=per)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -426,6 +435,22 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+def tune_lookup(p: int, q: int, r_b: int, precision: str = "fp32", arch: Optional[str] = None):
+    """The tuning cache's entry for a kernel class (see stap_tune_lookup):
+    dict(pix_per_item, grid_mult) or None."""
+    ppb, mult, found = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().stap_tune_lookup(arch.encode() if arch else None, p, q, r_b, PRECISIONS[precision],
+                                  ctypes.byref(ppb), ctypes.byref(mult), ctypes.byref(found)))
+    return dict(pix_per_item=ppb.value, grid_mult=mult.value) if found.value else None
+
+
+def tune_record(p: int, q: int, r_b: int, pix_per_item: int, grid_mult: int, precision: str = "fp32",
+                ms: float = 0.0, arch: Optional[str] = None):
+    """Records a tuning-cache entry (and rewrites KSTAP_TUNE_CACHE if set)."""
+    _check(lib().stap_tune_record(arch.encode() if arch else None, p, q, r_b, PRECISIONS[precision],
+                                  pix_per_item, grid_mult, ms))
 
 
 def version() -> str:

@@ -18,6 +18,7 @@
 #include "kstap_internal.h"
 
 #include "kstap_host.h"
+#include "kstap_tune.h"
 
 using namespace kstap::host;
 
@@ -27,6 +28,8 @@ namespace {
 struct BatchClass {
   int cls = -1;                  // kernel class
   std::vector<int32_t> order;    // tiles of this class, longest first
+  int ppb = 16;                  // work-item size (tiled-order positions, a multiple of the chain)
+  int grid_mult = 1;             // persistent grid = compute units x 8 x grid_mult
 };
 
 int device_cus() {
@@ -36,8 +39,6 @@ int device_cus() {
   return cus;
 }
 
-std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune_cache;   // signature -> (ppb, grid multiplier)
 
 // Split planes of the mixed path for stap_run / stap_probe come from a
 // stream-ordered pool per device that keeps its memory between calls
@@ -103,9 +104,6 @@ struct stap_batch_s {
   std::vector<kstap::KParams> descs;
   std::vector<BatchClass> classes;
   int64_t pixels = 0;
-  int ppb = 16;
-  int grid_mult = 1;
-  std::string signature;
   // device
   void* d_buf = nullptr;         // descs | order | prefix | counters
   void* d_planes = nullptr;      // split planes of the mixed-path tiles
@@ -133,7 +131,7 @@ void batch_release_graph(stap_batch_s* b) {
   b->graph = nullptr;
 }
 
-// Numbers the work items for the current ppb and uploads the prefix tables.
+// Numbers the work items of every class for its ppb and uploads the prefix tables.
 stap_status batch_tables(stap_batch_s* b) {
   std::vector<int64_t> prefix;
   b->prefix_base.clear();
@@ -143,7 +141,7 @@ stap_status batch_tables(stap_batch_s* b) {
     for (int32_t t : c.order) {
       prefix.push_back(acc);
       const int64_t px = b->descs[t].range_end - b->descs[t].range_first;
-      acc += (px + b->ppb - 1) / b->ppb;
+      acc += (px + c.ppb - 1) / c.ppb;
     }
     prefix.push_back(acc);
   }
@@ -159,7 +157,7 @@ stap_status batch_build(stap_batch_s* b) {
   batch_release_graph(b);
   stap_status st = batch_tables(b);
   if (st != STAP_OK) return st;
-  const int grid = device_cus() * 8 * b->grid_mult;
+  const int cus = device_cus();
   hipGraph_t g = nullptr;
   hipError_t e = hipGraphCreate(&g, 0);
   if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "graph create: %s", hipGetErrorString(e));
@@ -196,12 +194,12 @@ stap_status batch_build(stap_batch_s* b) {
     const int32_t* order = b->d_order + b->order_base[i];
     const int64_t* prefix = b->d_prefix + b->prefix_base[i];
     int nt = int(c.order.size());
-    int ppb = b->ppb;
+    int ppb = c.ppb;
     unsigned long long* counter = b->d_counters + i * kstap::kQueues;
     void* args[] = {&descs, &order, &prefix, &nt, &ppb, &counter};
     hipKernelNodeParams np{};
     np.func = const_cast<void*>(kstap::persistent_kernel(c.cls));
-    np.gridDim = dim3(grid);
+    np.gridDim = dim3(cus * 8 * c.grid_mult);
     np.blockDim = dim3(64);
     np.sharedMemBytes = 0;
     np.kernelParams = args;
@@ -222,18 +220,21 @@ stap_status batch_build(stap_batch_s* b) {
   return STAP_OK;
 }
 
-// The same work launched directly on `s` (used by the tuner, so that timing
-// candidates needs no graph).
-stap_status batch_launch_direct(stap_batch_s* b, hipStream_t s) {
-  const int grid = device_cus() * 8 * b->grid_mult;
+// Work of the batch launched directly on `s` (used by the tuner, so that
+// timing candidates needs no graph): the split kernels if `splits`, then the
+// counter reset and the persistent kernel of class `only` (every class if -1).
+stap_status batch_launch_direct(stap_batch_s* b, hipStream_t s, bool splits = true, int only = -1) {
+  const int cus = device_cus();
   int le = hipSuccess;
-  for (size_t i = 0; i < b->splits.size() && le == hipSuccess; ++i)
+  for (size_t i = 0; splits && i < b->splits.size() && le == hipSuccess; ++i)
     le = kstap::launch_split(b->splits[i].x, b->splits[i].xs, b->splits[i].n, s);
   if (le == hipSuccess) le = kstap::launch_reset(b->d_counters, int(b->classes.size()) * kstap::kQueues, s);
   for (size_t i = 0; i < b->classes.size() && le == hipSuccess; ++i) {
+    if (only >= 0 && int(i) != only) continue;
     const BatchClass& c = b->classes[i];
     le = kstap::launch_persistent(c.cls, b->d_descs, b->d_order + b->order_base[i], b->d_prefix + b->prefix_base[i],
-                                  int(c.order.size()), b->ppb, b->d_counters + i * kstap::kQueues, grid, s);
+                                  int(c.order.size()), c.ppb, b->d_counters + i * kstap::kQueues,
+                                  cus * 8 * c.grid_mult, s);
   }
   if (le != hipSuccess) return fail(STAP_ERR_DEVICE, "batch launch: %s", hipGetErrorString(hipError_t(le)));
   return STAP_OK;
@@ -669,25 +670,20 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
       at += 2 * ((nt.second + 63) / 64 * 64);
     }
   }
-  char sig[64];
-  std::string signature;
+  // work-item size and grid per class: as given, else the tuned entry of the
+  // class for this device, else 16 positions and CUs x 8 workgroups
+  const std::string arch = kstap::tune::device_arch();
   for (BatchClass& c : b->classes) {
     std::stable_sort(c.order.begin(), c.order.end(), [&](int32_t a, int32_t z) { return cost[a] > cost[z]; });
-    snprintf(sig, sizeof(sig), "c%d:%zu;", c.cls, c.order.size());
-    signature += sig;
-  }
-  snprintf(sig, sizeof(sig), "px%lld", (long long)(b->pixels >> 16));
-  b->signature = signature + sig;
-  b->ppb = 16;
-  b->grid_mult = 1;
-  if (pix_per_item > 0) {
-    b->ppb = (pix_per_item + kstap::kChainNarrow - 1) / kstap::kChainNarrow * kstap::kChainNarrow;   // runs start on a chain
-  } else {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune_cache.find(b->signature);
-    if (it != g_tune_cache.end()) {
-      b->ppb = it->second.first;
-      b->grid_mult = it->second.second;
+    if (pix_per_item > 0) {
+      c.ppb = (pix_per_item + kstap::kChainNarrow - 1) / kstap::kChainNarrow * kstap::kChainNarrow;   // runs start on a chain
+    } else {
+      int cp, cq, crb, cprec;
+      kstap::tune::Entry e;
+      if (kstap::class_shape(c.cls, &cp, &cq, &crb, &cprec) && kstap::tune::lookup(arch, cp, cq, crb, cprec, &e)) {
+        c.ppb = e.ppb;
+        c.grid_mult = e.grid_mult;
+      }
     }
   }
   // device buffer: descs | order | prefix | counters
@@ -747,53 +743,115 @@ stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best
     (void)hipEventDestroy(e0);
     return fail(STAP_ERR_DEVICE, "event create failed");
   }
-  const int ppbs[] = {16, 32, 64};   // multiples of kstap::kChainNarrow
-  const int mults[] = {1, 2};
-  double best = 1e300;
-  int bp = batch->ppb, bm = batch->grid_mult;
-  stap_status st = STAP_OK;
-  for (int ppb : ppbs) {
-    for (int m : mults) {
-      batch->ppb = ppb;
-      batch->grid_mult = m;
-      st = batch_tables(batch);
-      if (st == STAP_OK) st = batch_launch_direct(batch, s);   // warm-up
-      hipError_t e = hipSuccess;
-      float ms = 0.f;
-      if (st == STAP_OK) e = hipEventRecord(e0, s);
-      for (int r = 0; r < 2 && st == STAP_OK && e == hipSuccess; ++r) st = batch_launch_direct(batch, s);
-      if (st == STAP_OK && e == hipSuccess) e = hipEventRecord(e1, s);
-      if (st == STAP_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-      if (st == STAP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  // per class: work items of 16..128 positions (multiples of the chain) x
+  // persistent grids of 1, 2, 4 x (CUs x 8) workgroups, the class alone
+  const int ppbs[] = {16, 32, 64, 128};
+  const int mults[] = {1, 2, 4};
+  stap_status st = batch_launch_direct(batch, s, true, int(batch->classes.size()));   // the splits only
+  double total = 0.0;
+  std::vector<std::pair<int, int>> best(batch->classes.size());
+  std::vector<double> best_t(batch->classes.size(), 1e300);
+  for (size_t i = 0; i < batch->classes.size() && st == STAP_OK; ++i) {
+    BatchClass& c = batch->classes[i];
+    best[i] = {c.ppb, c.grid_mult};
+    for (int ppb : ppbs) {
+      for (int m : mults) {
+        c.ppb = ppb;
+        c.grid_mult = m;
+        st = batch_tables(batch);
+        if (st == STAP_OK) st = batch_launch_direct(batch, s, false, int(i));   // warm-up
+        hipError_t e = hipSuccess;
+        float ms = 0.f;
+        if (st == STAP_OK) e = hipEventRecord(e0, s);
+        for (int r = 0; r < 2 && st == STAP_OK && e == hipSuccess; ++r) st = batch_launch_direct(batch, s, false, int(i));
+        if (st == STAP_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+        if (st == STAP_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+        if (st == STAP_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (st != STAP_OK) break;
+        if (e != hipSuccess) {
+          st = fail(STAP_ERR_DEVICE, "tuning launch: %s", hipGetErrorString(e));
+          break;
+        }
+        if (ms / 2.0 < best_t[i]) {
+          best_t[i] = ms / 2.0;
+          best[i] = {ppb, m};
+        }
+      }
       if (st != STAP_OK) break;
-      if (e != hipSuccess) {
-        st = fail(STAP_ERR_DEVICE, "tuning launch: %s", hipGetErrorString(e));
-        break;
-      }
-      if (ms / 2.0 < best) {
-        best = ms / 2.0;
-        bp = ppb;
-        bm = m;
-      }
     }
-    if (st != STAP_OK) break;
+    c.ppb = best[i].first;
+    c.grid_mult = best[i].second;
+    total += best_t[i];
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != STAP_OK) return st;
-  batch->ppb = bp;
-  batch->grid_mult = bm;
   hipError_t se = hipStreamSynchronize(s);
   if (se != hipSuccess) return fail(STAP_ERR_DEVICE, "tuning: %s", hipGetErrorString(se));
   st = batch_build(batch);
   if (st != STAP_OK) return st;
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune_cache[batch->signature] = {bp, bm};
+  const std::string arch = kstap::tune::device_arch();
+  for (size_t i = 0; i < batch->classes.size(); ++i) {
+    int cp, cq, crb, cprec;
+    if (!kstap::class_shape(batch->classes[i].cls, &cp, &cq, &crb, &cprec)) continue;
+    kstap::tune::Entry e;
+    e.ppb = best[i].first;
+    e.grid_mult = best[i].second;
+    e.ms = best_t[i];
+    std::string err;
+    if (!kstap::tune::record(arch, cp, cq, crb, cprec, e, &err)) return fail(STAP_ERR_INVALID_ARG, "%s", err.c_str());
   }
-  if (best_ppb) *best_ppb = bp;
-  if (best_grid_mult) *best_grid_mult = bm;
-  if (best_ms) *best_ms = best;
+  // the largest class's choice is reported (every class is in the cache)
+  size_t big = 0;
+  for (size_t i = 1; i < best_t.size(); ++i)
+    if (best_t[i] > best_t[big]) big = i;
+  if (best_ppb) *best_ppb = best.empty() ? 16 : best[big].first;
+  if (best_grid_mult) *best_grid_mult = best.empty() ? 1 : best[big].second;
+  if (best_ms) *best_ms = total;
+  return ok();
+}
+
+stap_status stap_batch_class_info(const stap_batch_t* batch, int32_t cls, int32_t* p, int32_t* q, int32_t* rb_bound,
+                                  int32_t* precision, int32_t* pix_per_item, int32_t* grid_mult) {
+  if (!batch || cls < 0 || cls >= int32_t(batch->classes.size()))
+    return fail(STAP_ERR_INVALID_ARG, "batch is NULL or class index out of range");
+  const BatchClass& c = batch->classes[size_t(cls)];
+  int cp = 0, cq = 0, crb = 0, cprec = 0;
+  (void)kstap::class_shape(c.cls, &cp, &cq, &crb, &cprec);
+  if (p) *p = cp;
+  if (q) *q = cq;
+  if (rb_bound) *rb_bound = crb;
+  if (precision) *precision = cprec;
+  if (pix_per_item) *pix_per_item = c.ppb;
+  if (grid_mult) *grid_mult = c.grid_mult;
+  return ok();
+}
+
+stap_status stap_tune_lookup(const char* arch, int32_t p, int32_t q, int32_t r_b, int32_t precision,
+                             int32_t* pix_per_item, int32_t* grid_mult, int32_t* found) {
+  if (!found) return fail(STAP_ERR_INVALID_ARG, "found is NULL");
+  const std::string a = arch ? std::string(arch) : kstap::tune::device_arch();
+  kstap::tune::Entry e;
+  *found = kstap::tune::lookup(a, p, q, r_b <= 4 ? 4 : 8, precision, &e) ? 1 : 0;
+  if (pix_per_item) *pix_per_item = *found ? e.ppb : 16;
+  if (grid_mult) *grid_mult = *found ? e.grid_mult : 1;
+  return ok();
+}
+
+stap_status stap_tune_record(const char* arch, int32_t p, int32_t q, int32_t r_b, int32_t precision,
+                             int32_t pix_per_item, int32_t grid_mult, double ms) {
+  if (pix_per_item < kstap::kChainNarrow || pix_per_item % kstap::kChainNarrow != 0 || pix_per_item > 4096)
+    return fail(STAP_ERR_INVALID_ARG, "pix_per_item must be a multiple of %d in [%d, 4096]", kstap::kChainNarrow,
+                kstap::kChainNarrow);
+  if (grid_mult < 1 || grid_mult > 64) return fail(STAP_ERR_INVALID_ARG, "grid_mult outside [1, 64]");
+  const std::string a = arch ? std::string(arch) : kstap::tune::device_arch();
+  if (a.empty()) return fail(STAP_ERR_INVALID_ARG, "no architecture given and no device");
+  kstap::tune::Entry e;
+  e.ppb = pix_per_item;
+  e.grid_mult = grid_mult;
+  e.ms = ms;
+  std::string err;
+  if (!kstap::tune::record(a, p, q, r_b <= 4 ? 4 : 8, precision, e, &err)) return fail(STAP_ERR_INVALID_ARG, "%s", err.c_str());
   return ok();
 }
 
@@ -802,8 +860,9 @@ stap_status stap_batch_info(const stap_batch_t* batch, int64_t* pixels, int32_t*
   if (!batch) return fail(STAP_ERR_INVALID_ARG, "batch is NULL");
   if (pixels) *pixels = batch->pixels;
   if (classes) *classes = int32_t(batch->classes.size());
-  if (pix_per_item) *pix_per_item = batch->ppb;
-  if (grid_mult) *grid_mult = batch->grid_mult;
+  // the first class's (every class's: stap_batch_class_info)
+  if (pix_per_item) *pix_per_item = batch->classes.empty() ? 16 : batch->classes[0].ppb;
+  if (grid_mult) *grid_mult = batch->classes.empty() ? 1 : batch->classes[0].grid_mult;
   return ok();
 }
 

@@ -85,6 +85,16 @@ int launch_persistent(int cls, const KParams* descs, const int32_t* order, const
   return table()[cls]->persist(descs, order, prefix, nt, ppb, counter, grid, stream);
 }
 
+bool class_shape(int cls, int* p, int* q, int* rbm, int* prec) {
+  if (cls < 0 || cls >= int(table().size())) return false;
+  const Entry* e = table()[cls];
+  *p = e->p;
+  *q = e->q;
+  *rbm = e->rbm;
+  *prec = e->prec;
+  return true;
+}
+
 const void* persistent_kernel(int cls) {
   if (cls < 0 || cls >= int(table().size())) return nullptr;
   return table()[cls]->persist_fn;

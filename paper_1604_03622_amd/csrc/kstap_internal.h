@@ -166,6 +166,9 @@ bool kernel_available(int p, int q, int r_b, int precision);
 // 2 * 4 bytes per complex sample of the frame, filled by launch_split.
 bool kernel_needs_planes(int p, int q, int r_b, int precision);
 
+// (p, q, r_b bound, precision) of a kernel class; false if out of range.
+bool class_shape(int cls, int* p, int* q, int* rbm, int* prec);
+
 // Enqueues the fused per-pixel kernel.  Returns a hipError_t value.
 int launch_pixels(int p, int q, int precision, int mode, const KParams& prm, hipStream_t stream);
 

@@ -66,7 +66,9 @@ def test_batch_equals_tiles_alone_and_oracle():
         assert torch.equal(t[2], t0)
     best = b.tune()
     print("tuned:", best, flush=True)
-    assert best["pix_per_item"] in (16, 32, 64) and best["grid_mult"] in (1, 2)
+    assert best["pix_per_item"] in (16, 32, 64, 128) and best["grid_mult"] in (1, 2, 4)
+    for c in b.info()["per_class"]:
+        assert c["pix_per_item"] in (16, 32, 64, 128) and c["grid_mult"] in (1, 2, 4)
     for t in tiles:
         t[2].fill_(-1.0)
     b.launch()
@@ -79,6 +81,43 @@ def test_batch_equals_tiles_alone_and_oracle():
     kstap.run_batch(tiles)
     for t, t0 in zip(tiles, T0):
         assert torch.equal(t[2], t0)
+
+
+def test_tune_cache_round_trip(tmp_path, monkeypatch):
+    """Tuning records one entry per kernel class in the cache file; a new
+    batch made with pix_per_item=0 takes each class's tuned values from it,
+    and its results stay bitwise those of the untuned batch."""
+    import json
+    kstap, tiles, _ = _setup(seed=9)
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("KSTAP_TUNE_CACHE", str(path))
+    b0 = kstap.Batch(tiles, pix_per_item=16)
+    b0.launch()
+    torch.cuda.synchronize()
+    T0 = [t[2].clone() for t in tiles]
+    D0 = [t[3].clone() for t in tiles]
+    b0.tune()
+    tuned = b0.info()["per_class"]
+    print("tuned per class:", tuned, flush=True)
+    del b0
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "kstap-tune-1"
+    keyed = {(e["p"], e["q"], e["rb_bound"], e["precision"]): (e["pix_per_item"], e["grid_mult"])
+             for e in doc["entries"]}
+    for c in tuned:
+        assert keyed[(c["p"], c["q"], c["rb_bound"], c["precision"])] == (c["pix_per_item"], c["grid_mult"])
+        prec = {v: k for k, v in kstap.PRECISIONS.items()}[c["precision"]]
+        assert kstap.tune_lookup(c["p"], c["q"], c["rb_bound"], prec) == dict(pix_per_item=c["pix_per_item"],
+                                                                             grid_mult=c["grid_mult"])
+    for t in tiles:
+        t[2].fill_(-1.0)
+        t[3].fill_(7)
+    b1 = kstap.Batch(tiles)
+    assert b1.info()["per_class"] == tuned
+    b1.launch()
+    torch.cuda.synchronize()
+    for t, t0, d0 in zip(tiles, T0, D0):
+        assert torch.equal(t[2], t0) and torch.equal(t[3], d0)
 
 
 def test_benchmark_batch_sampled_oracle_parity():
