@@ -221,6 +221,24 @@ typedef struct {
 stap_status stap_lrkron(const stap_lrk_config* cfg, const void* X, float* A, float* B, double* stats,
                         void* hip_stream);
 
+/* Size of the static work area of stap_run_noalloc, per device (bytes). */
+#define STAP_NOALLOC_MAX_BYTES (128u << 20)
+
+/* stap_run for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same whole-frame pass with the same arguments, results and errors, but the
+ * call allocates nothing.  The mixed path's split planes (8 bytes per complex
+ * sample of x) go to a static work area of STAP_NOALLOC_MAX_BYTES that each
+ * device holds from the library's first use on it until the process ends
+ * (FP32 plans need no work area).  A frame whose planes exceed it is refused
+ * with INVALID_ARG before anything is enqueued.  Every call on one device
+ * shares that device's area and it keeps the last call's contents: calls that
+ * overlap on one device (concurrent streams, or host threads without
+ * ordering) race and must be serialised by the caller; calls on one stream
+ * are ordered.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
+stap_status stap_run_noalloc(const stap_plan_t* plan, const void* x, int32_t H, int32_t W,
+                             float* T, uint8_t* D, void* hip_stream);
+
 /* Per-pixel probe: the same computation for a list of pixels, with the
  * intermediate results.  All pointers are device memory:
  *   pix   int32 [npix][2] (r, c)   (pixels outside the valid region get T = 0,

@@ -94,6 +94,7 @@ def lib() -> ctypes.CDLL:
         "stap_run": [p_, p_, i32, i32, p_, p_, p_],
         "stap_run_ex": [p_, p_, i32, i32, ctypes.POINTER(StapOutputs), p_],
         "stap_lrkron": [ctypes.POINTER(StapLrkConfig), p_, p_, p_, p_, p_],
+        "stap_run_noalloc": [p_, p_, i32, i32, p_, p_, p_],
         "stap_probe": [p_, p_, i32, i32, p_, i32, ctypes.POINTER(StapProbeOut), p_],
         "stap_run_batch": [ctypes.POINTER(StapTile), i32, p_],
         "stap_batch_create": [ctypes.POINTER(StapTile), i32, i32, ctypes.POINTER(p_)],
@@ -300,6 +301,27 @@ def lrkron(X, r_a: int = 1, eps: float = 1e-6, min_iter: int = 2, max_iter: int 
                              ctypes.c_void_p(B.data_ptr()) if B is not None else None,
                              ctypes.c_void_p(stats.data_ptr()), _stream_handle(stream)))
     return dict(A=A, B=B, stats=stats, _keep=X)
+
+
+NOALLOC_MAX_BYTES = 128 << 20
+
+
+def run_noalloc(plan: Plan, x, T, D=None, stream=None):
+    """stap_run_noalloc: the whole-frame pass into caller-provided T (float32
+    [H, W]) and D (uint8 [H, W] or None), with no device allocation in the
+    library (the mixed path's planes use a static per-device work area of
+    NOALLOC_MAX_BYTES; calls that overlap on one device race)."""
+    import torch
+    H, W = _check_frame(plan, x)
+    for name, t, dt in (("T", T, torch.float32), ("D", D, torch.uint8)):
+        if t is None and name == "D":
+            continue
+        if not isinstance(t, torch.Tensor) or t.dtype != dt or t.device != x.device or tuple(t.shape) != (H, W) \
+                or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} tensor [H, W] on the frame's device")
+    _check(lib().stap_run_noalloc(plan.handle, ctypes.c_void_p(x.data_ptr()), H, W, ctypes.c_void_p(T.data_ptr()),
+                                  ctypes.c_void_p(D.data_ptr()) if D is not None else None, _stream_handle(stream)))
+    return T, D
 
 
 def probe(plan: Plan, x, pix, stream=None) -> dict:

@@ -98,6 +98,37 @@ hipError_t planes_release(const kstap::KParams& k, hipStream_t s) {
   return k.xs ? hipFreeAsync(const_cast<uint32_t*>(k.xs), s) : hipSuccess;
 }
 
+// Work area of stap_run_noalloc: the split planes of the mixed path in memory
+// that is reserved with the code object, so that the call allocates nothing.
+// Each device that loads the library holds its own copy until the process
+// ends.  In host code `scratch` only names the symbol; the device address
+// comes from hipGetSymbolAddress, once per device, and only that address is
+// ever handed to a kernel.
+constexpr size_t kScratchBytes = size_t(STAP_NOALLOC_MAX_BYTES);
+static __device__ __align__(256) uint32_t scratch[kScratchBytes / sizeof(uint32_t)];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of its `scratch`
+
+stap_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return STAP_OK;
+  }
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(STAP_ERR_DEVICE, "work area address on device %d: %s", dev, hipGetErrorString(e));
+  g_scratch_ptr[dev] = ptr;
+  *out = ptr;
+  return STAP_OK;
+}
+
 }  // namespace
 
 struct stap_batch_s {
@@ -561,6 +592,39 @@ stap_status stap_lrkron(const stap_lrk_config* cfg, const void* X, float* A, flo
   k.stats = stats;
   const int e = kstap::launch_lrkron(static_cast<const float2*>(X), k, static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "large-q launch: %s", hipGetErrorString(hipError_t(e)));
+  return ok();
+}
+
+stap_status stap_run_noalloc(const stap_plan_t* plan, const void* x, int32_t H, int32_t W, float* T, uint8_t* D,
+                             void* hip_stream) {
+  stap_status st = check_frame(plan, x, H, W);
+  if (st != STAP_OK) return st;
+  if (!T) return fail(STAP_ERR_INVALID_ARG, "T is NULL");
+  const stap_config& c = plan->cfg;
+  kstap::KParams k;
+  fill_params(plan, x, H, W, &k);
+  k.T = T;
+  k.D = D;
+  const int64_t total = kstap::tiled_positions(H, W);
+  const int64_t ppb = (c.p * c.q > 64) ? kstap::kChainWide : kstap::kChainNarrow;
+  k.pix_per_block = int32_t(ppb);
+  k.nlogical = int32_t((total + ppb - 1) / ppb);
+  const hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (kstap::kernel_needs_planes(c.p, c.q, c.r_b, c.precision)) {
+    const int64_t n = int64_t(c.p) * H * W * c.q;
+    if (size_t(n) * 8 > kScratchBytes)
+      return fail(STAP_ERR_INVALID_ARG, "frame needs %lld bytes of split planes; the static work area holds %zu",
+                  (long long)(n * 8), kScratchBytes);
+    void* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != STAP_OK) return st;
+    const int le = kstap::launch_split(static_cast<const float2*>(x), static_cast<uint32_t*>(ws), n, s);
+    if (le != hipSuccess) return fail(STAP_ERR_DEVICE, "split launch: %s", hipGetErrorString(hipError_t(le)));
+    k.xs = static_cast<const uint32_t*>(ws);
+  }
+  const int e = kstap::launch_pixels(c.p, c.q, c.precision, kstap::kModeRun, k, s);
+  if (e != hipSuccess)
+    return fail(STAP_ERR_DEVICE, "kernel launch failed: %s", hipGetErrorString(static_cast<hipError_t>(e)));
   return ok();
 }
 
