@@ -15,10 +15,10 @@
 // B-hat, a rank-np product (kernel lrk_emit_b).
 //
 // lrk_solve: one workgroup.  All eight waves accumulate the Gram matrix of the
-// n p snapshot rows (FP64 sums of FP32 products, in LDS) and the row sums that
-// give the initialiser of Eq. (18); wave 0 then runs the iterations in FP64
-// with its lanes over (m, m') pairs and EIG_{r_a} by cyclic Jacobi rotations
-// (lane k updates row and column k), with no workgroup barrier.
+// n p snapshot rows (FP64 sums of FP32 products) and the row sums that give
+// the initialiser of Eq. (18), then run the iterations in FP64: the n^2 block
+// products over all threads, EIG_{r_a} by cyclic Jacobi rotations on wave 0
+// with the p x p matrix in registers.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -54,70 +54,109 @@ __device__ __forceinline__ void lane_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Eigen-decomposition of the Hermitian p x p matrix H (LDS, overwritten) by
-// cyclic Jacobi rotations, run by one wavefront with lane k < p updating row
-// and column k; V (LDS) receives the eigenvectors as columns, lam (LDS) the
-// eigenvalues (unsorted).  Each rotation U = D [c s; -s c] on the pair (a, b),
-// D = diag(1, e^{-i phi}) making H[a][b] real, zeroes H[a][b]: H <- U^H H U.
-__device__ void jacobi_herm(dc* H, dc* V, double* lam, int p, int lane) {
-  if (lane < p)
-    for (int j = 0; j < p; ++j) V[lane * p + j] = mk(lane == j ? 1.0 : 0.0, 0.0);
-  lane_sync();
+// Partner of index k in round s of the circle schedule over PE (even)
+// indices: index 0 stays, the others rotate, position t meets position
+// PE - 1 - t.  Over PE - 1 rounds every pair meets once.
+__device__ __forceinline__ int rr_partner(int k, int s, int PE) {
+  const int m = PE - 1;
+  const int pos = (k == 0) ? 0 : 1 + ((k - 1 - s) % m + m) % m;
+  const int t = PE - 1 - pos;
+  return (t == 0) ? 0 : 1 + (t - 1 + s) % m;
+}
+
+__device__ __forceinline__ dc shd(dc x, int src) { return mk(__shfl(x.x, src, 64), __shfl(x.y, src, 64)); }
+
+// Eigen-decomposition of a Hermitian P x P matrix by Jacobi rotations in
+// parallel order, run by one wavefront with one lane per matrix entry: lane
+// r PE + c holds h = H[r][c] and v = V[r][c] (PE = P rounded up to even; a
+// zero pad row and column when P is odd, which no rotation touches).  Each
+// round applies PE / 2 rotations on disjoint index pairs at once, and each
+// rotation U = D [c s; -s c] on the pair (a, b), a < b, D = diag(1, e^{-i phi})
+// making H[a][b] real, zeroes H[a][b]: H <- U^H H U, V <- V U.  On return the
+// diagonal lanes hold the eigenvalues (unsorted) and V the eigenvectors as
+// columns.
+template <int P>
+__device__ __forceinline__ void jacobi_par(dc& h, dc& v, int lane) {
+  constexpr int PE = (P + 1) / 2 * 2;
+  const bool in = lane < PE * PE;
+  const int r = in ? lane / PE : 0, c = in ? lane - (lane / PE) * PE : 0;
+  v = mk((in && r == c) ? 1.0 : 0.0, 0.0);
+  if (!in) h = mk(0, 0);
   for (int sweep = 0; sweep < 30; ++sweep) {
-    double off = 0, tot = 0;
-    for (int i = 0; i < p; ++i)
-      for (int j = 0; j < p; ++j) {
-        tot += ab2(H[i * p + j]);
-        if (i != j) off += ab2(H[i * p + j]);
-      }
-    if (off <= 1e-30 * tot) break;   // uniform: every lane reads the same LDS values
-    for (int a = 0; a < p - 1; ++a)
-      for (int b = a + 1; b < p; ++b) {
-        const dc hab = H[a * p + b];
-        const double r = sqrt(ab2(hab));
-        if (r <= 1e-300 * sqrt(tot)) continue;
-        const dc e = scl(hab, 1.0 / r);   // e^{i phi}
-        const double tau = (H[b * p + b].x - H[a * p + a].x) / (2.0 * r);
+    const double m2 = ab2(h);
+    const double off = wave_sum(r != c ? m2 : 0.0), tot = wave_sum(m2);
+    if (off <= 1e-30 * tot) break;   // uniform
+    const double small = 1e-300 * sqrt(tot);
+    for (int s = 0; s < PE - 1; ++s) {
+      // U[k][k] (us) and U[partner][k] (uo) of the rotation that holds index k
+      auto params = [&](int k, int kp, dc& us, dc& uo) {
+        const int a = min(k, kp), b = max(k, kp);
+        const dc hab = shd(h, a * PE + b);
+        const double haa = shd(h, a * PE + a).x, hbb = shd(h, b * PE + b).x;
+        const double rr = sqrt(ab2(hab));
+        if (rr <= small) {
+          us = mk(1, 0);
+          uo = mk(0, 0);
+          return;
+        }
+        const dc e = scl(hab, 1.0 / rr);   // e^{i phi}
+        const double tau = (hbb - haa) / (2.0 * rr);
         const double t = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-        const double c = 1.0 / sqrt(1.0 + t * t), sn = t * c;
-        const dc ec = cj(e);
-        lane_sync();
-        if (lane < p) {   // columns: H <- H U, V <- V U
-          const int k = lane;
-          const dc ha = H[k * p + a], hb = H[k * p + b];
-          H[k * p + a] = sub(scl(ha, c), scl(mul(ec, hb), sn));
-          H[k * p + b] = add(scl(ha, sn), scl(mul(ec, hb), c));
-          const dc va = V[k * p + a], vb = V[k * p + b];
-          V[k * p + a] = sub(scl(va, c), scl(mul(ec, vb), sn));
-          V[k * p + b] = add(scl(va, sn), scl(mul(ec, vb), c));
+        const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+        if (k == a) {   // column a of U: (c, -s conj(e))
+          us = mk(cs, 0);
+          uo = scl(cj(e), -sn);
+        } else {        // column b of U: (s, c conj(e))
+          us = scl(cj(e), cs);
+          uo = mk(sn, 0);
         }
-        lane_sync();
-        if (lane < p) {   // rows: H <- U^H H
-          const int k = lane;
-          const dc ha = H[a * p + k], hb = H[b * p + k];
-          H[a * p + k] = sub(scl(ha, c), scl(mul(e, hb), sn));
-          H[b * p + k] = add(scl(ha, sn), scl(mul(e, hb), c));
-        }
-        lane_sync();
-        if (lane == 0) {
-          H[a * p + b] = mk(0, 0);
-          H[b * p + a] = mk(0, 0);
-          H[a * p + a].y = 0;
-          H[b * p + b].y = 0;
-        }
-        lane_sync();
-      }
+      };
+      const int rp = rr_partner(r, s, PE), cp = rr_partner(c, s, PE);
+      dc usr, uor, usc, uoc;
+      params(r, rp, usr, uor);
+      params(c, cp, usc, uoc);
+      const dc h_rcp = shd(h, r * PE + cp), h_rpc = shd(h, rp * PE + c), h_rpcp = shd(h, rp * PE + cp);
+      const dc v_rcp = shd(v, r * PE + cp);
+      // H'[r][c] = sum over s in {r, r'}, t in {c, c'} of conj(U[s][r]) H[s][t] U[t][c]
+      const dc t1 = add(mul(h, usc), mul(h_rcp, uoc));
+      const dc t2 = add(mul(h_rpc, usc), mul(h_rpcp, uoc));
+      dc hn = add(mul(cj(usr), t1), mul(cj(uor), t2));
+      const dc vn = add(mul(v, usc), mul(v_rcp, uoc));
+      if (r != c && c == rp) hn = mk(0, 0);   // the rotated pair's off-diagonal entries
+      if (r == c) hn.y = 0;
+      h = in ? hn : mk(0, 0);
+      v = in ? vn : mk(0, 0);
+    }
   }
-  if (lane < p) lam[lane] = H[lane * p + lane].x;
-  lane_sync();
 }
 
 constexpr int kSolveThreads = 512;
 constexpr int kSolveWaves = kSolveThreads / 64;
-constexpr int kChunk = 128;   // samples per staged chunk (64 rows x 128 x 8 bytes = 64 KB)
+constexpr int kStageMax = 8192;             // staged samples per chunk (n p rows x chunk length)
+constexpr int kPre = kStageMax / kSolveThreads;                 // staged samples per thread
+constexpr int kMaxEnt = (kLrkMaxRows * (kLrkMaxRows + 1) / 2 + kLrkMaxRows + kSolveThreads - 1) / kSolveThreads;
+// LDS region shared by the phases: the staged chunk (Gram), then the pair
+// products T and the partial sums of M and tb (iterations).
+constexpr size_t kOffT = 0;
+constexpr size_t kOffPm = sizeof(dc) * kLrkMaxRows * kLrkMaxRows;    // after T (n^2 p^2 <= 64^2 entries)
+constexpr size_t kOffPt = kOffPm + sizeof(dc) * kSolveThreads;
+constexpr size_t kRegion = kOffPt + sizeof(double) * kSolveThreads;
+static_assert(sizeof(float2) * (kStageMax + kLrkMaxRows) <= kRegion, "staged chunk fits the shared region");
 
 // P: channels, a compile-time constant so that the p x p matrices of the
 // iteration live in registers.
+//
+// Gram phase: entry e of the upper triangle (or row sum) of the n p snapshot
+// rows belongs to one thread per sample group; every thread keeps its FP64
+// sums of FP32 products in registers over all chunks (the chunks, as long as
+// the LDS region allows for n p rows, are staged through LDS with the next
+// one's global loads in flight while the current one is consumed) and the
+// groups are added once at the end.
+//
+// Iterations: all threads form the n^2 products T_(m,m') = G_m'm A, then the
+// partial sums of M = sum T_(m,m') G_mm' and tb = Re sum tr(T_(m,m') T_(m',m))
+// over pair subsets; wave 0 adds them, takes EIG_{r_a} (parallel Jacobi, one
+// lane per matrix entry) and the stop decision.
 template <int P>
 __global__ __launch_bounds__(kSolveThreads) void lrk_solve(const float2* __restrict__ X, LrkParams prm) {
   constexpr int p = P;
@@ -128,84 +167,149 @@ __global__ __launch_bounds__(kSolveThreads) void lrk_solve(const float2* __restr
   __shared__ dc sA[kLrkMaxP * kLrkMaxP], sAp[kLrkMaxP * kLrkMaxP];
   __shared__ dc sH[kLrkMaxP * kLrkMaxP], sV[kLrkMaxP * kLrkMaxP], sM[kLrkMaxP * kLrkMaxP];
   __shared__ double sLam[kLrkMaxP];
-  __shared__ float2 sX[kLrkMaxRows * kChunk];    // staged samples of every snapshot row
+  __shared__ int sStop;
+  __shared__ __align__(16) char sReg[kRegion];
+  float2* const sX = reinterpret_cast<float2*>(sReg);
+  dc* const sT = reinterpret_cast<dc*>(sReg + kOffT);
+  dc* const sPm = reinterpret_cast<dc*>(sReg + kOffPm);
+  double* const sPt = reinterpret_cast<double*>(sReg + kOffPt);
 
-  // ---- Gram matrix (upper triangle) and row sums, FP64 sums of FP32 products.
-  // The snapshot rows are staged through LDS in chunks of kChunk samples
-  // (coalesced loads by the whole workgroup); entry e of the Gram (or a row
-  // sum) belongs to wave e % 8, whose lanes split the chunk's samples and add
-  // the chunk's sum into the LDS entry.
+  // ---- Gram matrix (upper triangle) and row sums
   const int ntri = np * (np + 1) / 2, nent = ntri + np;
-  for (int e = tid; e < np * np; e += kSolveThreads) sG[e] = mk(0, 0);
-  for (int e = tid; e < np; e += kSolveThreads) sRow[e] = mk(0, 0);
-  for (int k0 = 0; k0 < q; k0 += kChunk) {
-    const int len = min(kChunk, q - k0);
-    __syncthreads();   // the previous chunk is consumed (and the sums above zeroed)
-    for (int e = tid; e < np * kChunk; e += kSolveThreads) {
-      const int u = e / kChunk, k = e - (e / kChunk) * kChunk;
-      sX[u * kChunk + k] = (k < len) ? X[int64_t(u) * q + k0 + k] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    for (int e = wave; e < nent; e += kSolveWaves) {
-      int u, v;
-      const bool rowsum = e >= ntri;
-      if (rowsum) {
-        u = v = e - ntri;
-      } else {
-        // e -> (u, v), u <= v, row-major over the upper triangle
-        u = 0;
-        int rem = e;
+  const bool grouped = nent <= kSolveThreads;
+  const int G = grouped ? kSolveThreads / nent : 1;   // sample groups
+  const int grp = grouped ? tid / nent : 0;
+  int eu[kMaxEnt], ev[kMaxEnt];   // row u, column v of each entry (v < 0: row sum of u)
+  int ne = 0;
+#pragma unroll
+  for (int j = 0; j < kMaxEnt; ++j) {
+    const int e = grouped ? (j == 0 && grp < G ? tid - grp * nent : nent) : tid + j * kSolveThreads;
+    eu[j] = 0;
+    ev[j] = -1;
+    if (e < nent) {
+      ne = j + 1;
+      if (e >= ntri) {
+        eu[j] = e - ntri;
+      } else {   // e -> (u, v), u <= v, row-major over the upper triangle
+        int u = 0, rem = e;
         while (rem >= np - u) {
           rem -= np - u;
           ++u;
         }
-        v = u + rem;
+        eu[j] = u;
+        ev[j] = u + rem;
       }
-      double sr = 0, si = 0;
-      for (int k = lane; k < len; k += 64) {
-        const float2 a = sX[u * kChunk + k];
-        if (rowsum) {
-          sr += double(a.x);
-          si += double(a.y);
-        } else {
-          const float2 b = sX[v * kChunk + k];   // a * conj(b)
-          sr += double(a.x) * double(b.x) + double(a.y) * double(b.y);
-          si += double(a.y) * double(b.x) - double(a.x) * double(b.y);
+    }
+  }
+  double ar[kMaxEnt], ai[kMaxEnt];
+#pragma unroll
+  for (int j = 0; j < kMaxEnt; ++j) ar[j] = ai[j] = 0.0;
+
+  // chunk length: a power of two from 128 to 1024 with n p x chunk <= kStageMax
+  int lch = 7;
+  while (lch < 10 && (np << (lch + 1)) <= kStageMax) ++lch;
+  const int chunk = 1 << lch, pitch = chunk + 1;   // padded LDS row (float2)
+  float2 pre[kPre];   // element tid + 512 j of the chunk: row e >> lch, sample e & (chunk - 1)
+  auto load_chunk = [&](int k0) {
+    const int len = min(chunk, q - k0);
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) {
+      const int e = tid + j * kSolveThreads, u = e >> lch, k = e & (chunk - 1);
+      pre[j] = (u < np && k < len) ? X[int64_t(u) * q + k0 + k] : make_float2(0.f, 0.f);
+    }
+  };
+  const int nch = (q + chunk - 1) / chunk;
+  load_chunk(0);
+  for (int ch = 0; ch < nch; ++ch) {
+    const int len = min(chunk, q - ch * chunk);
+    __syncthreads();   // the previous chunk is consumed
+#pragma unroll
+    for (int j = 0; j < kPre; ++j) {
+      const int e = tid + j * kSolveThreads, u = e >> lch, k = e & (chunk - 1);
+      if (u < np) sX[u * pitch + k] = pre[j];
+    }
+    __syncthreads();
+    if (ch + 1 < nch) load_chunk((ch + 1) * chunk);
+    if (grouped) {
+      // one entry per thread: four independent sums in flight
+      if (ne > 0) {
+        const float2* const ra = sX + eu[0] * pitch;
+        const bool rowsum = ev[0] < 0;
+        const float2* const rb = sX + (rowsum ? eu[0] : ev[0]) * pitch;
+        double xr[4] = {0, 0, 0, 0}, xi[4] = {0, 0, 0, 0};
+        int k = grp;
+        for (; k + 3 * G < len; k += 4 * G) {
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            const float2 a = ra[k + t * G];
+            const float2 b = rowsum ? make_float2(1.f, 0.f) : rb[k + t * G];   // a * conj(b)
+            xr[t] += double(a.x) * double(b.x) + double(a.y) * double(b.y);
+            xi[t] += double(a.y) * double(b.x) - double(a.x) * double(b.y);
+          }
         }
+        for (; k < len; k += G) {
+          const float2 a = ra[k];
+          const float2 b = rowsum ? make_float2(1.f, 0.f) : rb[k];
+          xr[0] += double(a.x) * double(b.x) + double(a.y) * double(b.y);
+          xi[0] += double(a.y) * double(b.x) - double(a.x) * double(b.y);
+        }
+        ar[0] += (xr[0] + xr[1]) + (xr[2] + xr[3]);
+        ai[0] += (xi[0] + xi[1]) + (xi[2] + xi[3]);
       }
-      sr = wave_sum(sr);
-      si = wave_sum(si);
-      if (lane == 0) {   // one writer per entry
-        if (rowsum) {
-          sRow[u] = add(sRow[u], mk(sr, si));
-        } else {
-          sG[u * np + v] = add(sG[u * np + v], mk(sr, si));
-          if (v != u) sG[v * np + u] = add(sG[v * np + u], mk(sr, -si));
+    } else {
+      for (int k = 0; k < len; ++k) {
+#pragma unroll
+        for (int j = 0; j < kMaxEnt; ++j) {
+          if (j < ne) {
+            const float2 a = sX[eu[j] * pitch + k];
+            const float2 b = ev[j] >= 0 ? sX[ev[j] * pitch + k] : make_float2(1.f, 0.f);   // a * conj(b)
+            ar[j] += double(a.x) * double(b.x) + double(a.y) * double(b.y);
+            ai[j] += double(a.y) * double(b.x) - double(a.x) * double(b.y);
+          }
         }
       }
     }
   }
-  __syncthreads();
-  // ---- the iterations: wave 0 alone, lanes over (m, m') pairs
-  if (wave != 0) return;
-
-  auto G = [&](int m, int mm, int i, int j) -> dc { return sG[(m * p + i) * np + mm * p + j]; };
-  const int npair = n * n;
-
-  // ||R||^2 = ||S||^2 = (1/n^2) sum_{m,m'} |tr G_m'm|^2
-  double nr = 0;
-  for (int t = lane; t < npair; t += 64) {
-    const int m = t / n, mm = t - (t / n) * n;
-    dc tr = mk(0, 0);
-    for (int i = 0; i < p; ++i) tr = add(tr, G(mm, m, i, i));
-    nr += ab2(tr);
+  __syncthreads();   // the staged chunk is dead: its region takes the group partials
+  auto put = [&](int u, int v, dc s) {
+    if (v < 0) {
+      sRow[u] = s;
+    } else {
+      sG[u * np + v] = s;
+      if (v != u) sG[v * np + u] = cj(s);
+    }
+  };
+  if (grouped) {
+    if (ne > 0) sPm[tid] = mk(ar[0], ai[0]);
+    __syncthreads();
+    if (tid < nent) {
+      dc s = mk(0, 0);
+      for (int g2 = 0; g2 < G; ++g2) s = add(s, sPm[g2 * nent + tid]);
+      put(eu[0], ev[0], s);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < kMaxEnt; ++j)
+      if (j < ne) put(eu[j], ev[j], mk(ar[j], ai[j]));
   }
-  const double normR2 = wave_sum(nr) / (double(n) * n);
+  __syncthreads();
 
-  // initialiser (Eq. (18)): A0 = (1/(n q^2)) sum_m s_m s_m^H, s_m the row sums;
-  // fallback R vec(I_q) = (1/n) sum_m G_mm when ||A0|| is negligible.
-  // Lane e < p^2 holds entry (e / p, e % p).
-  {
+  auto G_ = [&](int m, int mm, int i, int j) -> dc { return sG[(m * p + i) * np + mm * p + j]; };
+  const int npair = n * n;
+  double normR2 = 0;
+  if (wave == 0) {
+    // ||R||^2 = ||S||^2 = (1/n^2) sum_{m,m'} |tr G_m'm|^2
+    double nr = 0;
+    for (int t = lane; t < npair; t += 64) {
+      const int m = t / n, mm = t - (t / n) * n;
+      dc tr = mk(0, 0);
+      for (int i = 0; i < p; ++i) tr = add(tr, G_(mm, m, i, i));
+      nr += ab2(tr);
+    }
+    normR2 = wave_sum(nr) / (double(n) * n);
+    // initialiser (Eq. (18)): A0 = (1/(n q^2)) sum_m s_m s_m^H, s_m the row
+    // sums; fallback R vec(I_q) = (1/n) sum_m G_mm when ||A0|| is negligible.
+    // Lane e < p^2 holds entry (e / p, e % p).
     double an = 0;
     if (lane < p * p) {
       const int i = lane / p, j = lane - (lane / p) * p;
@@ -218,108 +322,119 @@ __global__ __launch_bounds__(kSolveThreads) void lrk_solve(const float2* __restr
     if (an <= 1e-24 * normR2 && lane < p * p) {
       const int i = lane / p, j = lane - (lane / p) * p;
       dc s = mk(0, 0);
-      for (int m = 0; m < n; ++m) s = add(s, G(m, m, i, j));
+      for (int m = 0; m < n; ++m) s = add(s, G_(m, m, i, j));
       sA[lane] = scl(s, 1.0 / n);
     }
-    lane_sync();
+    if (lane == 0) sStop = !(normR2 > 0.0);
   }
+  __syncthreads();
+  const bool zero = sStop != 0;
 
   double eta = 0, eta_prev = INFINITY, bn2 = 0;
   int iters = 0;
-  const bool zero = !(normR2 > 0.0);
+  constexpr int PP = P * P;
+  constexpr int kSplit = kSolveThreads / PP;   // pair subsets of the partial sums
   while (!zero) {
-    double an2 = 0;
-    for (int e = 0; e < P * P; ++e) an2 += ab2(sA[e]);
-    const double c = 1.0 / (double(n) * an2);
-    // M = sum G_m'm A G_mm' and tb = Re sum tr(A G_mm' A G_m'm), one row i of
-    // M at a time: each lane accumulates its pairs' contributions to row i,
-    // the row is summed over the wave into LDS (few live registers at any P)
-    double tb = 0;
-    for (int i = 0; i < P; ++i) {
-      dc out[P];
+    // T_(m,m') = G_m'm A, pair t = m n + m'
+    for (int task = tid; task < npair * PP; task += kSolveThreads) {
+      const int t = task / PP, ik = task - t * PP, i = ik / P, k = ik - i * P;
+      const int m = t / n, mm = t - m * n;
+      dc s = mk(0, 0);
 #pragma unroll
-      for (int j = 0; j < P; ++j) out[j] = mk(0, 0);
-      for (int t = lane; t < npair; t += 64) {
-        const int m = t / n, mm = t - (t / n) * n;
-        dc r1[P];   // row i of G_m'm A
-#pragma unroll
-        for (int k = 0; k < P; ++k) {
-          dc s = mk(0, 0);
-#pragma unroll
-          for (int l = 0; l < P; ++l) s = add(s, mul(G(mm, m, i, l), sA[l * P + k]));
-          r1[k] = s;
-        }
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-          dc s = mk(0, 0);
-#pragma unroll
-          for (int k = 0; k < P; ++k) s = add(s, mul(r1[k], G(m, mm, k, j)));
-          out[j] = add(out[j], s);
-        }
-        // row i of A G_mm' against column i of A G_m'm
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-          dc t2 = mk(0, 0), t3 = mk(0, 0);
-#pragma unroll
-          for (int k = 0; k < P; ++k) {
-            t2 = add(t2, mul(sA[i * P + k], G(m, mm, k, j)));
-            t3 = add(t3, mul(sA[j * P + k], G(mm, m, k, i)));
-          }
-          tb += mul(t2, t3).x;
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const dc v = mk(wave_sum(out[j].x), wave_sum(out[j].y));
-        if (lane == 0) sM[i * P + j] = v;
-      }
+      for (int l = 0; l < P; ++l) s = add(s, mul(G_(mm, m, i, l), sA[l * P + k]));
+      sT[task] = s;
     }
-    tb = wave_sum(tb);
-    lane_sync();
-    bn2 = c * c * tb;                           // ||b||^2
-    const double sa = c / (double(n) * bn2);    // A' = R conj(b) / ||b||^2 = sa M
-    // EIG_{r_a} of the Hermitian part of A'
-    if (lane < p * p) {
-      const int i = lane / p, j = lane - (lane / p) * p;
-      sAp[lane] = scl(sM[lane], sa);
-      sH[lane] = scl(add(scl(sM[i * p + j], sa), cj(scl(sM[j * p + i], sa))), 0.5);
-    }
-    lane_sync();
-    jacobi_herm(sH, sV, sLam, p, lane);
-    // the r_a largest algebraic eigenvalues (uniform selection on every lane)
-    dc anew = mk(0, 0);
+    __syncthreads();
+    // partial sums of M[i][j] = sum_t (T_t G_mm')[i][j] and of
+    // tb = Re sum_t tr(T_(m,m') T_(m',m)) (this thread's term: entry (i, j))
     {
-      unsigned used = 0;
-      const int i = lane / p, j = lane - (lane / p) * p;
-      for (int r = 0; r < prm.r_a; ++r) {
-        int best = -1;
-        for (int k = 0; k < p; ++k)
-          if (!((used >> k) & 1u) && (best < 0 || sLam[k] > sLam[best])) best = k;
-        used |= 1u << best;
-        if (lane < p * p) anew = add(anew, scl(mul(sV[i * p + best], cj(sV[j * p + best])), sLam[best]));
+      dc pm = mk(0, 0);
+      double pt = 0;
+      const int o = tid % PP, s = tid / PP;
+      if (s < kSplit) {
+        const int i = o / P, j = o - (o / P) * P;
+        for (int t = s; t < npair; t += kSplit) {
+          const int m = t / n, mm = t - m * n;
+#pragma unroll
+          for (int k = 0; k < P; ++k) pm = add(pm, mul(sT[t * PP + i * P + k], G_(m, mm, k, j)));
+          pt += mul(sT[t * PP + i * P + j], sT[(mm * n + m) * PP + j * P + i]).x;
+        }
       }
+      sPm[tid] = pm;
+      sPt[tid] = pt;
     }
-    lane_sync();
-    double na = 0, cross = 0;
-    if (lane < p * p) {
-      sA[lane] = anew;
-      na = ab2(anew);
-      cross = mul(cj(anew), sAp[lane]).x;
+    __syncthreads();
+    if (wave == 0) {
+      double an2 = 0;
+      for (int e = 0; e < PP; ++e) an2 += ab2(sA[e]);
+      const double c = 1.0 / (double(n) * an2);
+      double tb = 0;
+      for (int j = lane; j < kSolveThreads; j += 64) tb += sPt[j];
+      tb = wave_sum(tb);
+      if (lane < PP) {
+        dc s = mk(0, 0);
+        for (int g2 = 0; g2 < kSplit; ++g2) s = add(s, sPm[g2 * PP + lane]);
+        sM[lane] = s;
+      }
+      lane_sync();
+      bn2 = c * c * tb;                           // ||b||^2
+      const double sa = c / (double(n) * bn2);    // A' = R conj(b) / ||b||^2 = sa M
+      // EIG_{r_a} of the Hermitian part of A'
+      if (lane < PP) {
+        const int i = lane / p, j = lane - (lane / p) * p;
+        sAp[lane] = scl(sM[lane], sa);
+        sH[lane] = scl(add(scl(sM[i * p + j], sa), cj(scl(sM[j * p + i], sa))), 0.5);
+      }
+      lane_sync();
+      {
+        constexpr int PE = (P + 1) / 2 * 2;
+        const int r = lane / PE, cc = lane - (lane / PE) * PE;
+        const bool real = r < P && cc < P;   // not the pad row or column, nor past PE^2
+        dc h = real ? sH[r * P + cc] : mk(0, 0), v;
+        jacobi_par<P>(h, v, lane);
+        if (real) {
+          sV[r * P + cc] = v;
+          if (r == cc) sLam[r] = h.x;
+        }
+      }
+      lane_sync();
+      // the r_a largest algebraic eigenvalues (uniform selection on every lane)
+      dc anew = mk(0, 0);
+      {
+        unsigned used = 0;
+        const int i = lane / p, j = lane - (lane / p) * p;
+        for (int r = 0; r < prm.r_a; ++r) {
+          int best = -1;
+          for (int k = 0; k < p; ++k)
+            if (!((used >> k) & 1u) && (best < 0 || sLam[k] > sLam[best])) best = k;
+          used |= 1u << best;
+          if (lane < PP) anew = add(anew, scl(mul(sV[i * p + best], cj(sV[j * p + best])), sLam[best]));
+        }
+      }
+      lane_sync();
+      double na = 0, cross = 0;
+      if (lane < PP) {
+        sA[lane] = anew;
+        na = ab2(anew);
+        cross = mul(cj(anew), sAp[lane]).x;
+      }
+      na = wave_sum(na);
+      cross = wave_sum(cross);
+      ++iters;
+      // eta^2 = (||R||^2 - 2 ||b||^2 Re<A, A'> + ||A||^2 ||b||^2) / ||R||^2
+      const double r2 = normR2 - 2.0 * bn2 * cross + na * bn2;
+      const double e = sqrt(fmax(r2, 0.0) / normR2);
+      eta = e;
+      const bool stop =
+          iters >= prm.max_iter || (prm.eps > 0.0 && iters >= prm.min_iter && fabs(e - eta_prev) <= prm.eps);
+      eta_prev = e;
+      if (lane == 0) sStop = stop ? 1 : 0;
     }
-    na = wave_sum(na);
-    cross = wave_sum(cross);
-    lane_sync();
-    ++iters;
-    // eta^2 = (||R||^2 - 2 ||b||^2 Re<A, A'> + ||A||^2 ||b||^2) / ||R||^2
-    const double r2 = normR2 - 2.0 * bn2 * cross + na * bn2;
-    const double e = sqrt(fmax(r2, 0.0) / normR2);
-    eta = e;
-    const bool stop =
-        iters >= prm.max_iter || (prm.eps > 0.0 && iters >= prm.min_iter && fabs(e - eta_prev) <= prm.eps);
-    if (stop) break;
-    eta_prev = e;
+    __syncthreads();
+    if (sStop) break;
   }
-  if (lane < p * p) prm.A[lane] = zero ? make_float2(0.f, 0.f) : make_float2(float(sA[lane].x), float(sA[lane].y));
+  if (wave != 0) return;
+  if (lane < PP) prm.A[lane] = zero ? make_float2(0.f, 0.f) : make_float2(float(sA[lane].x), float(sA[lane].y));
   if (lane == 0 && prm.stats) {
     prm.stats[0] = zero ? 0.0 : eta;
     prm.stats[1] = double(iters);
