@@ -359,3 +359,103 @@ def large_q_snapshots(p: int, q: int, n: int, r_a: int = 1, cnr_db: float = 30.0
     noise = (rng.standard_normal((n, p, q)) + 1j * rng.standard_normal((n, p, q))) / np.sqrt(2.0)
     X = np.matmul(root_a[None], w) + noise          # rows of A^(1/2) W have covariance A (x) I
     return X.astype(np.complex64)
+
+
+# ------------------------------------------------ SIRV texture, robustness
+@dataclasses.dataclass(frozen=True)
+class SirvSpec:
+    """Clutter with random texture (Sec. 2, Eq. (4)): per pixel
+    x = tau * c + noise with speckle c ~ CN(0, A (x) B), noise ~ CN(0, I) and
+    texture tau^2 ~ Gamma(shape nu, scale 1/nu), so E[tau^2] = 1 and the
+    clutter amplitude is K-distributed (texture_nu = None: tau = 1).  A has
+    rank r_a, B rank r_b, scaled to E[tau^2] tr(A (x) B) / (p q) = 10^(CNR/10).
+
+    Robustness setting: `n_test` test pixels (seeded, at least `margin` from
+    the border) carry no target; around each, `n_corrupt` moving targets
+    alpha a(theta) (x) b(f) (Eq. (8); a_i = exp(j i theta),
+    b_k = exp(2 pi j f k)) are added at distinct offsets with Chebyshev
+    distance in [inner, radius], i.e. inside the pixel's training window."""
+    p: int = 3
+    q: int = 16
+    H: int = 96
+    W: int = 96
+    r_a: int = 1
+    r_b: int = 3
+    cnr_db: float = 30.0
+    texture_nu: Optional[float] = 0.5
+    n_test: int = 64
+    margin: int = 16
+    n_corrupt: int = 0
+    radius: int = 7
+    inner: int = 2
+    corrupt_snr_db: float = 20.0
+    corrupt_theta: float = 1.0
+    corrupt_f: float = 0.25
+
+
+@dataclasses.dataclass
+class SirvScene:
+    spec: SirvSpec
+    seed: int
+    x: np.ndarray                    # complex64 [p][H][W][q]
+    tau2: np.ndarray                 # float64 [H][W]: the texture power of each pixel
+    test_pixels: np.ndarray          # int32 [n_test, 2]
+    corrupt: np.ndarray              # int64 [n_test * n_corrupt, 2]
+    UA: np.ndarray                   # [p, r_a] orthonormal; A = UA diag(lamA) UA^H
+    lamA: np.ndarray
+    UB: np.ndarray                   # [q, r_b] orthonormal; B = UB diag(lamB) UB^H
+    lamB: np.ndarray
+    sigma2: float = 1.0              # noise power
+    tau2_mean: float = 1.0           # E[tau^2]
+
+
+def spatial_steering(p: int, theta: float) -> np.ndarray:
+    """a(theta)_i = exp(j i theta), i = 0..p-1 (Eq. (8))."""
+    return np.exp(1j * theta * np.arange(p))
+
+
+def doppler_steering(q: int, f: float) -> np.ndarray:
+    """b(f)_k = exp(2 pi j f k), k = 0..q-1: a constant Doppler shift f
+    (cycles per sample) over the q samples."""
+    return np.exp(2j * np.pi * f * np.arange(q))
+
+
+def make_sirv_scene(spec: SirvSpec, seed: int = BASE_SEED) -> SirvScene:
+    """Draw one SIRV frame with optional training-window corruption.
+    Deterministic in (spec, seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    p, q, H, W = spec.p, spec.q, spec.H, spec.W
+    ua = _unitary_q(rng, p, spec.r_a)
+    ub = _unitary_q(rng, q, spec.r_b)
+    la = rng.uniform(0.5, 1.0, spec.r_a)
+    lb = rng.uniform(0.5, 1.0, spec.r_b)
+    lb = lb * (10.0 ** (spec.cnr_db / 10.0) * p * q / (la.sum() * lb.sum()))
+    root = np.kron(ua * np.sqrt(la), ub * np.sqrt(lb))              # [pq, r_a r_b]: A (x) B = root root^H
+    npx = H * W
+    rk = root.shape[1]
+    w = (rng.standard_normal((npx, rk)) + 1j * rng.standard_normal((npx, rk))) / np.sqrt(2.0)
+    noise = (rng.standard_normal((npx, p * q)) + 1j * rng.standard_normal((npx, p * q))) / np.sqrt(2.0)
+    if spec.texture_nu is None:
+        tau2 = np.ones(npx)
+    else:
+        tau2 = rng.gamma(spec.texture_nu, 1.0 / spec.texture_nu, npx)
+    snap = np.sqrt(tau2)[:, None] * (w @ root.T) + noise
+    x = np.ascontiguousarray(snap.reshape(H, W, p, q).transpose(2, 0, 1, 3)).astype(np.complex64)
+    m = spec.margin
+    tr = rng.integers(m, H - m, spec.n_test)
+    tc = rng.integers(m, W - m, spec.n_test)
+    offs = [(dr, dc) for dr in range(-spec.radius, spec.radius + 1) for dc in range(-spec.radius, spec.radius + 1)
+            if max(abs(dr), abs(dc)) >= spec.inner]
+    corrupt = []
+    if spec.n_corrupt > 0:
+        d = np.kron(spatial_steering(p, spec.corrupt_theta), doppler_steering(q, spec.corrupt_f))
+        amp = np.sqrt(10.0 ** (spec.corrupt_snr_db / 10.0))
+        for t in range(spec.n_test):
+            pick = rng.choice(len(offs), spec.n_corrupt, replace=False)
+            for k in pick:
+                r, c = tr[t] + offs[k][0], tc[t] + offs[k][1]
+                phase = rng.uniform(0.0, 2.0 * np.pi)
+                x[:, r, c, :] += (amp * np.exp(1j * phase) * d).reshape(p, q).astype(np.complex64)
+                corrupt.append((r, c))
+    return SirvScene(spec=spec, seed=seed, x=x, tau2=tau2.reshape(H, W), test_pixels=np.stack([tr, tc], 1).astype(np.int32),
+                     corrupt=np.array(corrupt, dtype=np.int64).reshape(-1, 2), UA=ua, lamA=la, UB=ub, lamB=lb)
