@@ -438,6 +438,68 @@ def form_variants(kstap, torch):
     return out
 
 
+def form_robustness(kstap, torch, cpu=True):
+    """Robustness evaluation (Sec. 2 SIRV model, Sec. 5 filters): a 256 x 256
+    p=3 q=16 scene with K-distributed texture (nu = 0.5) and, around each of
+    64 test pixels, 6 movers at 25 dB inside the training window, all with
+    the steering a(1.2) (x) b(0.2).  Times the LR-STAP baseline on every valid
+    pixel and the SINR-loss kernel on the test pixels over 2 x 65 steerings,
+    and reports the mean SINR loss of Kron-STAP, the classical joint
+    projector and LR-STAP (rank r_a r_b and r_a r_b + 1) at the movers'
+    steering and over the Doppler grid."""
+    spec = scenegen.SirvSpec(p=3, q=16, H=256, W=256, r_b=4, texture_nu=0.5, n_test=64, margin=16, n_corrupt=6,
+                             radius=7, corrupt_snr_db=25.0, corrupt_theta=1.2, corrupt_f=0.2)
+    sc = scenegen.make_sirv_scene(spec, seed=scenegen.BASE_SEED + 1300)
+    n, ra, rb = 200, 1, 4
+    plan = kstap.Plan(p=3, q=16, n=n, r_a=ra, r_b=rb)
+    x = torch.from_numpy(sc.x).cuda()
+    r0, r1, c0, c1 = plan.valid_region(spec.H, spec.W)
+    rr, cc = np.meshgrid(np.arange(r0, r1), np.arange(c0, c1), indexing="ij")
+    allpix = np.stack([rr.ravel(), cc.ravel()], 1).astype(np.int32)
+    pix_t = torch.from_numpy(allpix).cuda()
+    sec_lr = _timed(torch, lambda: kstap.lrstap_probe(plan, x, pix_t, r=ra * rb), 3)
+    pq = 3 * 16
+    scm_flops = 8.0 * n * pq * (pq + 1) / 2                     # FP32 S accumulation, upper triangle
+    out = dict(workload="SIRV 256x256 p=3 q=16 n=200, K-distributed texture nu=0.5, 6 movers (25 dB) in the "
+                        "training window of each of 64 test pixels",
+               lrstap=dict(pixels=int(len(allpix)), pixels_per_s=len(allpix) / sec_lr, ms=sec_lr * 1e3,
+                           scm_tflops=len(allpix) * scm_flops / sec_lr / 1e12,
+                           note="one 64-lane workgroup per pixel; S by VALU (FP32), subspace iteration FP64"))
+    _log(f"robustness: LR-STAP {len(allpix) / sec_lr / 1e6:.2f} Mpx/s")
+    tp = sc.test_pixels
+    pr = kstap.probe(plan, x, tp)
+    lr = {r: kstap.lrstap_probe(plan, x, tp, r=r) for r in (ra * rb, ra * rb + 1)}
+    fgrid = np.linspace(-0.5, 0.5, 65)
+    a_grid = np.stack([scenegen.spatial_steering(3, t) for t in (1.2, 2.5)]).astype(np.complex64)
+    b_grid = np.stack([scenegen.doppler_steering(16, f) for f in fgrid]).astype(np.complex64)
+    tc = (sc.UA.astype(np.complex64), sc.lamA, sc.UB.astype(np.complex64), sc.lamB, sc.sigma2, sc.tau2_mean)
+    losses = {k: kstap.sinr_loss(k, a_grid, b_grid, *tc, UA=pr["U_A"], UB=pr["U_B"]) for k in ("kron", "classical")}
+    for r, o in lr.items():
+        losses[f"lrstap_r{r}"] = kstap.sinr_loss("lrstap", a_grid, b_grid, *tc, U=o["U"])
+    sec_s = _timed(torch, lambda: kstap.sinr_loss("kron", a_grid, b_grid, *tc, UA=pr["U_A"], UB=pr["U_B"]), 5)
+    fi = int(np.argmin(np.abs(fgrid - 0.2)))
+    db = lambda v: float(10.0 * np.log10(max(float(v), 1e-30)))  # noqa: E731
+    curves = {}
+    for k, L in losses.items():
+        Lc = L.cpu().numpy()
+        curves[k] = dict(at_movers_db=db(Lc[:, 0, fi].mean()), mean_db_theta1p2=db(Lc[:, 0, :].mean()),
+                         mean_db_theta2p5=db(Lc[:, 1, :].mean()),
+                         curve_db_theta1p2=[round(db(v), 3) for v in Lc[:, 0, :].mean(axis=0)])
+    out["sinr"] = dict(test_pixels=int(len(tp)), steerings=int(a_grid.shape[0] * b_grid.shape[0]),
+                       evaluations_per_s=len(tp) * a_grid.shape[0] * b_grid.shape[0] / sec_s, ms=sec_s * 1e3,
+                       doppler_grid=[float(f) for f in fgrid], curves=curves)
+    _log("robustness: loss at the movers' steering (dB): " +
+         ", ".join(f"{k} {v['at_movers_db']:.1f}" for k, v in curves.items()))
+    if cpu:
+        import oracle
+        import oracle.robustness as RB
+        cfg = oracle.OracleConfig(p=3, q=16, n=n, r_a=ra, r_b=rb)
+        t0 = time.perf_counter()
+        RB.lr_stap_pixels(sc.x, allpix[:2000], cfg, r=ra * rb)
+        out["lrstap"]["oracle_pixels_per_s_one_process"] = 2000 / (time.perf_counter() - t0)
+    return out
+
+
 def system_forms(kstap, torch, args, scene):
     forms = {}
     forms["frame_bf16x3"] = form_frame_mixed(kstap, torch, scene, max(3, args.steps // 2))
@@ -452,6 +514,8 @@ def system_forms(kstap, torch, args, scene):
     forms["large_q"] = form_large_q(kstap, torch, cpu=not args.no_cpu)
     torch.cuda.empty_cache()
     forms["variants"] = form_variants(kstap, torch)
+    torch.cuda.empty_cache()
+    forms["robustness"] = form_robustness(kstap, torch, cpu=not args.no_cpu)
     return forms
 
 
@@ -468,7 +532,7 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
-    ap.add_argument("--only-form", choices=("large_q", "variants"),
+    ap.add_argument("--only-form", choices=("large_q", "variants", "robustness"),
                     help="run one secondary form alone and print its JSON (for kernel profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -483,6 +547,8 @@ def main():
         import paper_1604_03622_amd as kstap
         if args.only_form == "large_q":
             out = form_large_q(kstap, torch, cpu=False)
+        elif args.only_form == "robustness":
+            out = form_robustness(kstap, torch, cpu=False)
         else:
             out = form_variants(kstap, torch)
         if args.calibrate_copy:

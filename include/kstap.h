@@ -263,6 +263,84 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
                        const int32_t* pix, int32_t npix, const stap_probe_out* out,
                        void* hip_stream);
 
+/* Unstructured low-rank STAP baseline (LR-STAP), the classical method the
+ * Kronecker filters are compared with (Sec. 1; its filter is the
+ * unstructured counterpart of the joint projector of Eq. (24)): per pixel of
+ * a list, the sample covariance S of Eq. (2) over the plan's training
+ * stencil, the eigenvectors U of its r largest eigenvalues, the filter
+ * F = I - U U^H and the statistic max over spatial steerings h of
+ * |d^H F x|^2 / (d^H F d), d = h (x) b_s, with the plan's temporal steering
+ * (the pseudo-inverse form: eigenvalues of E^H F E at or below
+ * 1e-12 ||b_s||^2 dropped).  Under white noise the statistic is Gamma(p, 1).
+ *   r         rank; < 0: r_a * r_b of the plan (the rank of A (x) B);
+ *             0 <= r <= min(8, p q)
+ *   max_iter  subspace iterations (each: S times the p q x r basis, then
+ *             Gram-Schmidt twice), >= 1; 0: 300
+ *   tol       stop when the squared sines of the principal angles between
+ *             successive bases sum to at most tol^2; <= 0: 1e-7
+ * S is summed in FP32, the iteration, the Rayleigh-Ritz ordering of U and
+ * the statistic run in FP64.  All pointers are device memory:
+ *   pix   int32 [npix][2] (r, c)   (pixels outside the valid region get
+ *                                   T = 0, zero U and lam, iters = 0)
+ *   T     float [npix]
+ *   U     complex64 [npix][p q][r], columns ordered by decreasing eigenvalue,
+ *         rows in the vec(X^T) order (index i q + k), or NULL
+ *   lam   float [npix][r]: the Rayleigh-Ritz eigenvalues, decreasing, or NULL
+ *   iters int32 [npix]: iterations run (max_iter when not converged), or NULL
+ * Limits: p q <= 64, the plan's single temporal steering and GLRT statistic
+ * (plans with the fixed-steering statistic, a Doppler bank or several
+ * passes are refused with UNSUPPORTED).  Enqueued on hip_stream; allocates
+ * nothing.  Errors: INVALID_ARG, UNSUPPORTED, DEVICE. */
+typedef struct {
+  int32_t r;
+  int32_t max_iter;
+  double tol;
+} stap_lrstap_config;
+
+stap_status stap_lrstap_probe(const stap_plan_t* plan, const stap_lrstap_config* cfg, const void* x,
+                              int32_t H, int32_t W, const int32_t* pix, int32_t npix, float* T, float* U,
+                              float* lam, int32_t* iters, void* hip_stream);
+
+/* Output SINR loss of per-pixel filters (Sec. 5): for filter F and target
+ * steering d, SINR_out = |w^H d|^2 / (w^H Sigma w) with w = F d (Eqs. (21),
+ * (23), |alpha| = 1), divided by the optimum d^H Sigma^-1 d reached by
+ * F = Sigma^-1 (Eq. (22)); the loss lies in [0, 1] and is 0 where w = 0.
+ * The true clutter-plus-noise covariance of the SIRV model (Eqs. (5), (9))
+ * is Sigma = tau2 A (x) B + sigma2 I with A = UA diag(lamA) UA^H and
+ * B = UB diag(lamB) UB^H; UA and UB must have orthonormal columns (the
+ * optimum uses the Woodbury identity on that basis).  Steerings are all
+ * pairs d = a (x) b of a_grid [na][p] and b_grid [nb][q].
+ * Filters per pixel: KRON (I - P_A) (x) (I - P_B) (Eq. (25)) and CLASSICAL
+ * I - P_A (x) P_B (Eq. (24)) from bases UA [npix][p][r_a] and
+ * UB [npix][q][r_b] (as stap_probe writes them); LRSTAP I - U U^H from
+ * U [npix][p q][r] (as stap_lrstap_probe writes it).  All arrays are device
+ * memory, complex64 interleaved except lamA and lamB (double); output
+ * loss float [npix][na][nb].  Limits: 1 <= p <= 8, p q <= 64, sigma2 > 0,
+ * tau2 >= 0.  Allocates nothing.  Errors: INVALID_ARG, DEVICE. */
+typedef enum { STAP_SINR_KRON = 0, STAP_SINR_CLASSICAL = 1, STAP_SINR_LRSTAP = 2 } stap_sinr_filter;
+
+typedef struct {
+  int32_t p, q;
+  int32_t ra, rb;
+  const float* UA;
+  const double* lamA;
+  const float* UB;
+  const double* lamB;
+  double sigma2, tau2;
+} stap_true_cov;
+
+typedef struct {
+  int32_t filter;   /* stap_sinr_filter */
+  int32_t npix;
+  int32_t r_a, r_b, r;
+  const float* UA;
+  const float* UB;
+  const float* U;
+} stap_filter_set;
+
+stap_status stap_sinr_loss(const stap_true_cov* cov, const stap_filter_set* filters, const float* a_grid,
+                           int32_t na, const float* b_grid, int32_t nb, float* loss, void* hip_stream);
+
 /* Batched uneven tiles (tiles may differ in p, q, n, ranks, steering,
  * precision and size; each has its own plan, frame and outputs).
  *

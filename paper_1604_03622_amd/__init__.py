@@ -53,6 +53,24 @@ class StapLrkConfig(ctypes.Structure):
                 ("eps", ctypes.c_double), ("min_iter", ctypes.c_int32), ("max_iter", ctypes.c_int32)]
 
 
+class StapLrstapConfig(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class StapTrueCov(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("q", ctypes.c_int32), ("ra", ctypes.c_int32), ("rb", ctypes.c_int32),
+                ("UA", ctypes.c_void_p), ("lamA", ctypes.c_void_p), ("UB", ctypes.c_void_p), ("lamB", ctypes.c_void_p),
+                ("sigma2", ctypes.c_double), ("tau2", ctypes.c_double)]
+
+
+class StapFilterSet(ctypes.Structure):
+    _fields_ = [("filter", ctypes.c_int32), ("npix", ctypes.c_int32), ("r_a", ctypes.c_int32), ("r_b", ctypes.c_int32),
+                ("r", ctypes.c_int32), ("UA", ctypes.c_void_p), ("UB", ctypes.c_void_p), ("U", ctypes.c_void_p)]
+
+
+SINR_FILTERS = {"kron": 0, "classical": 1, "lrstap": 2}
+
+
 class StapOutputs(ctypes.Structure):
     _fields_ = [("T", ctypes.c_void_p), ("D", ctypes.c_void_p), ("E", ctypes.c_void_p), ("bin", ctypes.c_void_p),
                 ("Tpass", ctypes.c_void_p), ("C", ctypes.c_void_p)]
@@ -96,6 +114,8 @@ def lib() -> ctypes.CDLL:
         "stap_lrkron": [ctypes.POINTER(StapLrkConfig), p_, p_, p_, p_, p_],
         "stap_run_noalloc": [p_, p_, i32, i32, p_, p_, p_],
         "stap_probe": [p_, p_, i32, i32, p_, i32, ctypes.POINTER(StapProbeOut), p_],
+        "stap_lrstap_probe": [p_, ctypes.POINTER(StapLrstapConfig), p_, i32, i32, p_, i32, p_, p_, p_, p_, p_],
+        "stap_sinr_loss": [ctypes.POINTER(StapTrueCov), ctypes.POINTER(StapFilterSet), p_, i32, p_, i32, p_, p_],
         "stap_run_batch": [ctypes.POINTER(StapTile), i32, p_],
         "stap_batch_create": [ctypes.POINTER(StapTile), i32, i32, ctypes.POINTER(p_)],
         "stap_batch_launch": [p_, p_],
@@ -359,6 +379,65 @@ def run_batch(tiles, stream=None):
     """tiles: list of (plan, x, T, D) with torch tensors; one-shot batched run
     (creates, launches, synchronises and frees a Batch)."""
     _check(lib().stap_run_batch(_tile_array(tiles), len(tiles), _stream_handle(stream)))
+
+
+def lrstap_probe(plan: Plan, x, pix, r: int = -1, max_iter: int = 0, tol: float = 0.0, stream=None) -> dict:
+    """stap_lrstap_probe: the unstructured low-rank STAP baseline on pixels
+    pix [(r, c), ...] of a device frame.  Returns T [npix], U [npix, pq, r]
+    (complex64, columns by decreasing eigenvalue), lam [npix, r] and iters."""
+    import torch
+    H, W = _check_frame(plan, x)
+    dev = x.device
+    if isinstance(pix, torch.Tensor):
+        if pix.dtype != torch.int32 or pix.device != dev:
+            raise ValueError("pix must be an int32 tensor on the frame's device")
+        pix_t = pix.reshape(-1, 2).contiguous()
+    else:
+        pix_t = torch.as_tensor(np.asarray(pix, dtype=np.int32).reshape(-1, 2), device=dev).contiguous()
+    npix = int(pix_t.shape[0])
+    rr = plan.r_a * plan.r_b if r < 0 else int(r)
+    pq = plan.p * plan.q
+    T = torch.zeros(npix, dtype=torch.float32, device=dev)
+    U = torch.zeros((npix, pq, max(rr, 0)), dtype=torch.complex64, device=dev)
+    lam = torch.zeros((npix, max(rr, 0)), dtype=torch.float32, device=dev)
+    iters = torch.zeros(npix, dtype=torch.int32, device=dev)
+    cfg = StapLrstapConfig(int(r), int(max_iter), float(tol))
+    ptr = lambda t: ctypes.c_void_p(t.data_ptr()) if t.numel() else None  # noqa: E731
+    _check(lib().stap_lrstap_probe(plan.handle, ctypes.byref(cfg), ctypes.c_void_p(x.data_ptr()), H, W,
+                                   ptr(pix_t), npix, ptr(T), ptr(U), ptr(lam), ptr(iters), _stream_handle(stream)))
+    return dict(T=T, U=U, lam=lam, iters=iters, _keep=pix_t)
+
+
+def sinr_loss(filter: str, a_grid, b_grid, UA_true, lamA_true, UB_true, lamB_true, sigma2: float = 1.0,
+              tau2: float = 1.0, UA=None, UB=None, U=None, stream=None):
+    """stap_sinr_loss: SINR loss [npix, na, nb] (float32) of per-pixel
+    filters ('kron' / 'classical' from UA [npix, p, r_a] and UB [npix, q, r_b],
+    'lrstap' from U [npix, pq, r]; complex64 device tensors) for steerings
+    a (x) b over a_grid [na, p] x b_grid [nb, q], against the covariance
+    tau2 A (x) B + sigma2 I given by orthonormal bases and eigenvalues."""
+    import torch
+    dev = (U if filter == "lrstap" else UA).device
+    c64 = lambda a: torch.as_tensor(np.asarray(a, dtype=np.complex64), device=dev).contiguous()  # noqa: E731
+    f64 = lambda a: torch.as_tensor(np.asarray(a, dtype=np.float64), device=dev).contiguous()  # noqa: E731
+    ag, bg = c64(a_grid), c64(b_grid)
+    uat, ubt, lat, lbt = c64(UA_true), c64(UB_true), f64(lamA_true), f64(lamB_true)
+    p, ra = int(uat.shape[0]), int(uat.shape[1])
+    q, rb = int(ubt.shape[0]), int(ubt.shape[1])
+    na, nb = int(ag.shape[0]), int(bg.shape[0])
+    if filter == "lrstap":
+        U = U.contiguous()
+        npix, r_a, r_b, r = int(U.shape[0]), 0, 0, int(U.shape[2])
+    else:
+        UA, UB = UA.contiguous(), UB.contiguous()
+        npix, r_a, r_b, r = int(UA.shape[0]), int(UA.shape[2]), int(UB.shape[2]), 0
+    loss = torch.zeros((npix, na, nb), dtype=torch.float32, device=dev)
+    ptr = lambda t: t.data_ptr() if (t is not None and t.numel()) else None  # noqa: E731
+    cov = StapTrueCov(p, q, ra, rb, ptr(uat), ptr(lat), ptr(ubt), ptr(lbt), float(sigma2), float(tau2))
+    fs = StapFilterSet(SINR_FILTERS[filter], npix, r_a, r_b, r, ptr(UA), ptr(UB), ptr(U))
+    _check(lib().stap_sinr_loss(ctypes.byref(cov), ctypes.byref(fs), ctypes.c_void_p(ptr(ag)), na,
+                                ctypes.c_void_p(ptr(bg)), nb, ctypes.c_void_p(ptr(loss)), _stream_handle(stream)))
+    loss._keep = (ag, bg, uat, ubt, lat, lbt)
+    return loss
 
 
 class Batch:

@@ -659,6 +659,110 @@ stap_status stap_probe(const stap_plan_t* plan, const void* x, int32_t H, int32_
   return ok();
 }
 
+stap_status stap_lrstap_probe(const stap_plan_t* plan, const stap_lrstap_config* cfg, const void* x,
+                              int32_t H, int32_t W, const int32_t* pix, int32_t npix, float* T, float* U,
+                              float* lam, int32_t* iters, void* hip_stream) {
+  stap_status st = check_frame(plan, x, H, W);
+  if (st != STAP_OK) return st;
+  const stap_config& c = plan->cfg;
+  if (c.stat_mode != STAP_STAT_GLRT || c.nbank != 0 || c.passes != 1)
+    return fail(STAP_ERR_UNSUPPORTED, "LR-STAP takes the GLRT statistic of one temporal steering and one pass");
+  if (c.p * c.q > kstap::kLrsMaxPQ)
+    return fail(STAP_ERR_UNSUPPORTED, "LR-STAP needs p q <= %d (got %d)", kstap::kLrsMaxPQ, c.p * c.q);
+  if (npix < 0) return fail(STAP_ERR_INVALID_ARG, "npix < 0");
+  if (npix == 0) return ok();
+  if (!pix || !T) return fail(STAP_ERR_INVALID_ARG, "pix and T must not be NULL");
+  const int r = (!cfg || cfg->r < 0) ? c.r_a * c.r_b : cfg->r;
+  const int rmax = std::min(kstap::kLrsMaxR, c.p * c.q);
+  if (r < 0 || r > rmax) return fail(STAP_ERR_INVALID_ARG, "LR-STAP rank %d outside [0, %d]", r, rmax);
+  const int max_iter = (!cfg || cfg->max_iter == 0) ? 300 : cfg->max_iter;
+  if (max_iter < 1 || max_iter > 100000) return fail(STAP_ERR_INVALID_ARG, "max_iter %d outside [1, 100000]", max_iter);
+  const double tol = (!cfg || !(cfg->tol > 0.0)) ? 1e-7 : cfg->tol;
+  if (!std::isfinite(tol)) return fail(STAP_ERR_INVALID_ARG, "tol must be finite");
+  kstap::LrsParams k{};
+  k.x = static_cast<const float2*>(x);
+  k.H = H;
+  k.W = W;
+  k.p = c.p;
+  k.q = c.q;
+  k.n = c.n;
+  k.r = r;
+  k.max_iter = max_iter;
+  k.tol = tol;
+  valid_region(plan, H, W, &k.r0, &k.r1, &k.c0, &k.c1);
+  double bn = 0.0;
+  for (int j = 0; j < c.q; ++j) {
+    k.b_s[j] = make_float2(plan->b_steer[2 * j], plan->b_steer[2 * j + 1]);
+    bn += double(k.b_s[j].x) * k.b_s[j].x + double(k.b_s[j].y) * k.b_s[j].y;
+  }
+  k.bs_norm2 = bn;
+  for (int m = 0; m < c.n; ++m) {
+    k.st[2 * m] = int16_t(plan->stencil[2 * m]);
+    k.st[2 * m + 1] = int16_t(plan->stencil[2 * m + 1]);
+  }
+  k.pix = pix;
+  k.npix = npix;
+  k.T = T;
+  k.U = reinterpret_cast<float2*>(U);
+  k.lam = lam;
+  k.iters = iters;
+  const int e = kstap::launch_lrstap(k, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "LR-STAP launch: %s", hipGetErrorString(hipError_t(e)));
+  return ok();
+}
+
+stap_status stap_sinr_loss(const stap_true_cov* cov, const stap_filter_set* f, const float* a_grid, int32_t na,
+                           const float* b_grid, int32_t nb, float* loss, void* hip_stream) {
+  if (!cov || !f) return fail(STAP_ERR_INVALID_ARG, "cov and filters must not be NULL");
+  const int p = cov->p, q = cov->q;
+  if (p < 1 || p > 8 || q < 1 || p * q > 64) return fail(STAP_ERR_INVALID_ARG, "need 1 <= p <= 8 and p q <= 64");
+  if (cov->ra < 0 || cov->ra > p || cov->rb < 0 || cov->rb > q)
+    return fail(STAP_ERR_INVALID_ARG, "true factor ranks outside [0, p] x [0, q]");
+  if ((cov->ra > 0 && (!cov->UA || !cov->lamA)) || (cov->rb > 0 && (!cov->UB || !cov->lamB)))
+    return fail(STAP_ERR_INVALID_ARG, "true factor bases and eigenvalues must not be NULL");
+  if (!(cov->sigma2 > 0.0) || !std::isfinite(cov->sigma2) || !(cov->tau2 >= 0.0) || !std::isfinite(cov->tau2))
+    return fail(STAP_ERR_INVALID_ARG, "need sigma2 > 0 and tau2 >= 0");
+  if (f->filter < STAP_SINR_KRON || f->filter > STAP_SINR_LRSTAP) return fail(STAP_ERR_INVALID_ARG, "unknown filter");
+  if (f->npix < 0 || na < 0 || nb < 0) return fail(STAP_ERR_INVALID_ARG, "negative count");
+  if (f->npix == 0 || na == 0 || nb == 0) return ok();
+  if (!a_grid || !b_grid || !loss) return fail(STAP_ERR_INVALID_ARG, "a_grid, b_grid and loss must not be NULL");
+  if (f->filter == STAP_SINR_LRSTAP) {
+    if (f->r < 0 || f->r > p * q) return fail(STAP_ERR_INVALID_ARG, "r outside [0, p q]");
+    if (f->r > 0 && !f->U) return fail(STAP_ERR_INVALID_ARG, "U must not be NULL");
+  } else {
+    if (f->r_a < 0 || f->r_a > p || f->r_b < 0 || f->r_b > q)
+      return fail(STAP_ERR_INVALID_ARG, "r_a, r_b outside [0, p] x [0, q]");
+    if ((f->r_a > 0 && !f->UA) || (f->r_b > 0 && !f->UB)) return fail(STAP_ERR_INVALID_ARG, "UA and UB must not be NULL");
+  }
+  kstap::SinrParams k{};
+  k.kind = f->filter;
+  k.p = p;
+  k.q = q;
+  k.npix = f->npix;
+  k.r_a = f->r_a;
+  k.r_b = f->r_b;
+  k.r = f->r;
+  k.UA = reinterpret_cast<const float2*>(f->UA);
+  k.UB = reinterpret_cast<const float2*>(f->UB);
+  k.U = reinterpret_cast<const float2*>(f->U);
+  k.ra_t = cov->ra;
+  k.rb_t = cov->rb;
+  k.UA_t = reinterpret_cast<const float2*>(cov->UA);
+  k.lamA_t = cov->lamA;
+  k.UB_t = reinterpret_cast<const float2*>(cov->UB);
+  k.lamB_t = cov->lamB;
+  k.sigma2 = cov->sigma2;
+  k.tau2 = cov->tau2;
+  k.a_grid = reinterpret_cast<const float2*>(a_grid);
+  k.b_grid = reinterpret_cast<const float2*>(b_grid);
+  k.na = na;
+  k.nb = nb;
+  k.loss = loss;
+  const int e = kstap::launch_sinr(k, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return fail(STAP_ERR_DEVICE, "SINR launch: %s", hipGetErrorString(hipError_t(e)));
+  return ok();
+}
+
 stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pix_per_item, stap_batch_t** out) {
   if (!out) return fail(STAP_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;

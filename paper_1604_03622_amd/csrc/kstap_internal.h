@@ -78,6 +78,52 @@ struct LrkParams {
 };
 int launch_lrkron(const float2* X, const LrkParams& prm, hipStream_t stream);
 
+// Unstructured low-rank STAP baseline on a pixel list (stap_lrstap_probe):
+// per pixel the sample covariance over the plan's stencil, its top-r
+// eigenvectors by subspace iteration, and the statistic of the projector
+// I - U U^H.
+constexpr int kLrsMaxPQ = 64;
+constexpr int kLrsMaxR = 8;
+struct LrsParams {
+  const float2* x;        // frame, complex64 [p][H][W][q]
+  int32_t H, W, p, q, n, r;
+  int32_t max_iter;
+  double tol;
+  int32_t r0, r1, c0, c1; // valid region, half-open
+  double bs_norm2;
+  float2 b_s[kMaxQ];
+  int16_t st[2 * kMaxN];
+  const int32_t* pix;     // [npix][2]
+  int32_t npix;
+  float* T;               // [npix]
+  float2* U;              // [npix][pq][r] or null
+  float* lam;             // [npix][r] or null
+  int32_t* iters;         // [npix] or null
+};
+int launch_lrstap(const LrsParams& prm, hipStream_t stream);
+
+// Output SINR loss of per-pixel filters against a true covariance given in
+// factored form (stap_sinr_loss).
+struct SinrParams {
+  int32_t kind;           // 0: (I - P_A) (x) (I - P_B); 1: I - P_A (x) P_B; 2: I - U U^H
+  int32_t p, q, npix;
+  int32_t r_a, r_b, r;
+  const float2* UA;       // [npix][p][r_a]
+  const float2* UB;       // [npix][q][r_b]
+  const float2* U;        // [npix][pq][r]
+  int32_t ra_t, rb_t;
+  const float2* UA_t;     // [p][ra_t], orthonormal columns
+  const double* lamA_t;   // [ra_t]
+  const float2* UB_t;     // [q][rb_t], orthonormal columns
+  const double* lamB_t;   // [rb_t]
+  double sigma2, tau2;
+  const float2* a_grid;   // [na][p]
+  const float2* b_grid;   // [nb][q]
+  int32_t na, nb;
+  float* loss;            // [npix][na][nb]
+};
+int launch_sinr(const SinrParams& prm, hipStream_t stream);
+
 enum Mode { kModeRun = 0, kModeProbe = 1 };
 enum Move { kMoveRight = 0, kMoveLeft = 1, kMoveDown = 2 };
 
