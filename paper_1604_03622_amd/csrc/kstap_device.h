@@ -1295,6 +1295,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   // and runs start on a chain, so the choice is the same for every
   // decomposition.
   bool chain = false;
+  bool ua_ok = false;   // sUA holds the U_A of the pixel processed last
   for (int64_t it = 0; it < count; ++it) {
     int64_t idx;
     int r, c;
@@ -1475,10 +1476,14 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
         if (res) resid = wsumd(rr);
       };
 
-      // EIG_{r_a}: A <- U (U^H A' U) U^H with U the top-r_a subspace of Herm(A')
+      // EIG_{r_a}: A <- U (U^H A' U) U^H with U the top-r_a subspace of Herm(A').
+      // A pixel that slides from its predecessor starts from that pixel's
+      // U_A (sUA): the two training sets differ in a few vectors.  The choice
+      // depends only on the chain position, as the sliding window does.
+      const bool warm = slide && ua_ok;
       EC ua[P];
 #pragma unroll
-      for (int i = 0; i < P; ++i) ua[i] = czero<EC>();
+      for (int i = 0; i < P; ++i) ua[i] = warm ? sUA[i * RAM] : czero<EC>();
       auto eig_a = [&](bool cold) __attribute__((always_inline)) {
         EC Ah[P * P];
 #pragma unroll
@@ -1603,7 +1608,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       };
 
       sweep(false);
-      eig_a(true);
+      eig_a(!warm);
       iters = 1;
       double eta_prev = INFINITY;
       while (true) {
@@ -1619,6 +1624,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       }
       // bv now holds the final b = R^T conj(a) / ||a||^2
     }
+    ua_ok = !zero && !bad;
 
     // ------------------------------------------ enqueue for the batched tail
     wave_sync();   // S is dead from here on
