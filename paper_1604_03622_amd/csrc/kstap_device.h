@@ -36,6 +36,7 @@
 #include <stdint.h>
 
 #include "kstap_internal.h"
+#include "kstap_small_eig.h"
 
 namespace kstap {
 namespace {
@@ -1722,10 +1723,10 @@ __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restr
 }
 
 // ====================================================================
-// Wide pixels (p*q > 64): one 256-lane workgroup (4 wavefronts) per pixel.
+// Wide pixels (p*q > 64): one 512-lane workgroup (8 wavefronts) per pixel.
 //
 // The covariance tiles (16 x 16, upper block-triangle) are dealt round-robin
-// to the 4 waves.  Training vectors are staged in LDS 16 at a time (split
+// to the 8 waves.  Training vectors are staged in LDS 16 at a time (split
 // BF16 hi/lo pairs for PREC 1, FP32 for PREC 0), double-buffered: the global
 // loads of the next chunk are in flight while the waves run the MFMAs of the
 // current one.  S is kept as its upper q x q blocks S(i,j), i <= j (the lower
@@ -1733,12 +1734,18 @@ __global__ __launch_bounds__(64, 2) void kstap_persistent(const KParams* __restr
 // it outlives the pixel: in run mode every pixel of a sliding-window chain
 // but the first starts from the previous pixel's n*S (a one-pixel move) and
 // stages only the training vectors that enter the stencil (added) and leave
-// it (subtracted), as the narrow FP32 kernels do.  LR-Kron sweeps run over all 256 lanes with the
+// it (subtracted), as the narrow FP32 kernels do.  LR-Kron sweeps run over all 512 lanes with the
 // block sums reduced across waves through LDS; the small factor-A solves are
 // computed identically by every wave.  The Hermitian time factors are queued
-// in LDS and the batched tail (a6 + a8) runs 64/q' pixels per wave on all
-// four waves at once.
+// in LDS and the batched tail (a6 + a8) runs 64/q' pixels per wave on waves
+// 0-3 at once.  Eight waves (two per SIMD, the LDS footprint allows one
+// workgroup per compute unit) hide each other's LDS, reduction and barrier
+// latencies; with four, each SIMD ran a single wave.
 // ====================================================================
+constexpr int kWideWaves = 8;                      // waves per wide workgroup
+constexpr int kWideThreads = 64 * kWideWaves;
+constexpr int kTailWaves = 4;                      // waves that run the batched tail
+
 template <int P, int Q, int RBM, int PREC>
 struct WideLds {
   using EC = typename Pick<PREC == 1, double2, float2>::type;
@@ -1747,12 +1754,12 @@ struct WideLds {
   static constexpr int NBLK = P * (P + 1) / 2;
   static constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
   static constexpr int G = Groups<Q>::G;
-  static constexpr int NQ = 4 * G;                                   // pixels per batched tail
+  static constexpr int NQ = kTailWaves * G;                          // pixels per batched tail
   static constexpr size_t kS = sizeof(float2) * NBLK * Q * (Q + 1);  // upper blocks of S
   static constexpr size_t rowb = PREC ? 80 : 144;                    // padded bytes per staged row
   static constexpr size_t stage1 = PREC ? 2 * NB * 16 * rowb : NB * 16 * rowb;   // hi + lo, or fp32
   static constexpr size_t kStage = 2 * stage1;
-  static constexpr size_t kTail = sizeof(EC) * RBM * Q * G * 4;      // subspace scratch of the 4 waves
+  static constexpr size_t kTail = sizeof(EC) * RBM * Q * G * kTailWaves;   // subspace scratch of the tail waves
   static constexpr size_t kST = kStage > kTail ? kStage : kTail;
   static constexpr size_t oS = 0;
   static constexpr size_t oStage = (kS + 15) / 16 * 16;              // staging; tail scratch between pixels
@@ -1760,11 +1767,11 @@ struct WideLds {
   static constexpr size_t oQUA = oHq + sizeof(float2) * NQ * Q * Q;  // EC[NQ][P*RAM]: queued U_A
   static constexpr size_t oUA = oQUA + sizeof(EC) * NQ * P * RAM;    // EC[P*RAM]
   static constexpr size_t oAh = oUA + sizeof(EC) * P * RAM;          // EC[P*P]
-  static constexpr size_t oRedD = oAh + sizeof(EC) * P * P;          // double[4]
-  static constexpr size_t oQidx = oRedD + sizeof(double) * 4;        // int64[NQ]
-  static constexpr size_t oRed = oQidx + sizeof(int64_t) * NQ;       // float[4][KRED]
+  static constexpr size_t oRedD = oAh + sizeof(EC) * P * P;          // double[kWideWaves]
+  static constexpr size_t oQidx = oRedD + sizeof(double) * kWideWaves;   // int64[NQ]
+  static constexpr size_t oRed = oQidx + sizeof(int64_t) * NQ;       // float[kWideWaves][KRED]
   static constexpr int KRED = 2 * P * P + 8;
-  static constexpr size_t oA = oRed + sizeof(float) * 4 * KRED;      // float2[P*P]
+  static constexpr size_t oA = oRed + sizeof(float) * kWideWaves * KRED;   // float2[P*P]
   static constexpr size_t oAp = oA + sizeof(float2) * P * P;         // float2[P*P]: block sums (A_0, R b*)
   static constexpr size_t oB = oAp + sizeof(float2) * P * P;         // float2[Q*Q]: current b
   static constexpr size_t oOff = oB + sizeof(float2) * Q * Q;        // int[kMaxN]
@@ -1778,13 +1785,15 @@ struct WideLds {
 
 __device__ __forceinline__ void block_sync() { __syncthreads(); }
 
-// Sums a double over the 256 lanes of the workgroup (every lane gets the sum).
+// Sums a double over the lanes of the workgroup (every lane gets the sum).
 __device__ __forceinline__ double block_sumd(double v, double* red) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   v = wsumd(v);
   if (lane == 0) red[w] = v;
   block_sync();
-  v = (red[0] + red[1]) + (red[2] + red[3]);
+  v = 0.0;
+#pragma unroll
+  for (int i = 0; i < kWideWaves; ++i) v += red[i];
   block_sync();
   return v;
 }
@@ -1798,10 +1807,10 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
   constexpr int NB = L::NB;
   constexpr int QS = Q + 1;
   constexpr int QQ = Q * Q;
-  constexpr int NE = (QQ + 255) / 256;      // q x q entries per lane
+  constexpr int NE = (QQ + kWideThreads - 1) / kWideThreads;   // q x q entries per lane
   constexpr int RAM = L::RAM;
   constexpr int NPAIR = NB * (NB + 1) / 2;
-  constexpr int MYP = (NPAIR + 3) / 4;      // tile pairs per wave (round-robin)
+  constexpr int MYP = (NPAIR + kWideWaves - 1) / kWideWaves;   // tile pairs per wave (round-robin)
   constexpr int QP = Groups<Q>::QP;
   constexpr int G = L::G;
   constexpr int NQ = L::NQ;
@@ -1833,8 +1842,8 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
   // sample offsets of the stencil, and per one-pixel move those of the
   // entering then the leaving vectors
   block_sync();
-  for (int m = tid; m < n; m += 256) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
-  for (int m = tid; m < 6 * kMaxDelta; m += 256) {
+  for (int m = tid; m < n; m += kWideThreads) sOff[m] = (int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q;
+  for (int m = tid; m < 6 * kMaxDelta; m += kWideThreads) {
     const int mv = m / (2 * kMaxDelta), e = m - mv * (2 * kMaxDelta);
     int off = 0;
     if (prm.nadd[0] >= 0) {
@@ -1855,45 +1864,57 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     for (int I = 0; I < NB; ++I)
 #pragma unroll
       for (int J = I; J < NB; ++J, ++t) {
-        if ((t & 3) == wave) {
-          pI[t >> 2] = I;
-          pJ[t >> 2] = J;
+        if (t % kWideWaves == wave) {
+          pI[t / kWideWaves] = I;
+          pJ[t / kWideWaves] = J;
         }
       }
 #pragma unroll
-    for (int u = 0; u < MYP; ++u) pOk[u] = (u * 4 + wave) < NPAIR;
+    for (int u = 0; u < MYP; ++u) pOk[u] = (u * kWideWaves + wave) < NPAIR;
   }
 
-  // staging items of this thread: (vector v, row rho) = divmod(tid + 256 it, PQ),
-  // recomputed where used (cheaper than holding them in registers)
-  constexpr int NIT = (16 * PQ + 255) / 256;
+  constexpr int NIT = (16 * PQ + kWideThreads - 1) / kWideThreads;
   const int64_t plane = int64_t(H) * W * Q;
-  auto item = [&](int it, int* v, int* rho) __attribute__((always_inline)) -> bool {
-    const int e = tid + 256 * it;
-    *v = e / PQ;
-    *rho = e - *v * PQ;
-    return e < 16 * PQ;
-  };
 
   // ------------------------------------------ a6 + a8 for the queued pixels
-  // wave w serves queue slots w*G .. w*G + G - 1; lane k of a slot's group
-  // takes row k of its Hermitian time factor (column k, conjugated: the
-  // stored factor is exactly Hermitian)
+  // wave w < kTailWaves serves queue slots w*G .. w*G + G - 1; lane k of a
+  // slot's group takes row k of its Hermitian time factor (column k,
+  // conjugated: the stored factor is exactly Hermitian)
   auto tail = [&](int nfill) __attribute__((always_inline)) {
-    const int slot = wave * G + lane / QP, tk = lane % QP;
-    const bool own = slot < nfill && tk < Q;
-    float2 Bq[Q];
+    int lanev = threadIdx.x & 63;
+    asm volatile("" : "+v"(lanev));   // per call: no lane arithmetic hoisted out of the pixel loop
+    const int lane = lanev;
+    if (wave < kTailWaves) {   // uniform per wave; the tail syncs inside a wave only
+      const int slot = wave * G + lane / QP, tk = lane % QP;
+      const bool own = slot < nfill && tk < Q;
+      float2 Bq[Q];
 #pragma unroll
-    for (int l = 0; l < Q; ++l) Bq[l] = own ? cconj(sHq[(slot < nfill ? slot : 0) * QQ + l * Q + tk]) : cz();
-    EC* const scr = reinterpret_cast<EC*>(stage) + wave * (RBM * Q * G);
-    tail_batch<P, Q, RBM, MODE, EC, true, VAR>(prm, Bq, slot, nfill, sQflag, sQidx, sQeta, sQit, sQUA, scr,
-                                               PREC ? 1e-10 : 2e-6);
+      for (int l = 0; l < Q; ++l) Bq[l] = own ? cconj(sHq[(slot < nfill ? slot : 0) * QQ + l * Q + tk]) : cz();
+      EC* const scr = reinterpret_cast<EC*>(stage) + wave * (RBM * Q * G);
+      tail_batch<P, Q, RBM, MODE, EC, true, VAR>(prm, Bq, slot, nfill, sQflag, sQidx, sQeta, sQit, sQUA, scr,
+                                                 PREC ? 1e-10 : 2e-6);
+    }
     block_sync();
   };
 
   int nq = 0;
   bool chain = false;   // the previous position left a usable S in LDS
+  bool ua_ok = false;   // sUA holds the U_A of the pixel processed last
   auto pixel = [&](int64_t itp) __attribute__((always_inline)) {
+    // Opaque per-pixel copy of the thread index: the index arithmetic below
+    // (staging items, tile elements, q x q entries) is redone for every pixel
+    // rather than hoisted out of the pixel loop, where at two waves per SIMD
+    // it would not fit in registers.
+    int tidv = threadIdx.x;
+    asm volatile("" : "+v"(tidv));
+    const int tid = tidv, lane = tidv & 63;
+    // staging items of this thread: (vector v, row rho) = divmod(tid + 512 it, PQ)
+    auto item = [&](int it, int* v, int* rho) __attribute__((always_inline)) -> bool {
+      const int e = tid + kWideThreads * it;
+      *v = e / PQ;
+      *rho = e - *v * PQ;
+      return e < 16 * PQ;
+    };
     int64_t idx;
     int r, c;
     const bool left_ok = chain;
@@ -1918,9 +1939,9 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       }
       if (MODE == kModeProbe) {
         if (prm.UA)
-          for (int e = tid; e < P * r_a; e += 256) prm.UA[idx * P * r_a + e] = cz();
+          for (int e = tid; e < P * r_a; e += kWideThreads) prm.UA[idx * P * r_a + e] = cz();
         if (prm.UB)
-          for (int e = tid; e < Q * r_b; e += 256) prm.UB[idx * Q * r_b + e] = cz();
+          for (int e = tid; e < Q * r_b; e += kWideThreads) prm.UB[idx * Q * r_b + e] = cz();
       }
       return;
     }
@@ -1934,6 +1955,9 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     const int mv = tiled_move(first + itp, H, W, kChainWide);
     const bool slide = MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
     const int* const list = slide ? sDel + mv * 2 * kMaxDelta : sOff;
+    // EIG_{r_a} of a pixel that slides from its predecessor starts from that
+    // pixel's U_A (sUA); the choice follows the chain, as the sliding window
+    const bool warm = slide && ua_ok;
     const int cnt = slide ? prm.nadd[mv] + prm.nrem[mv] : n;
     const int npos = slide ? prm.nadd[mv] : n;
     const float fn = float(n);
@@ -2078,13 +2102,13 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     };
 
     // Block pass: out[ij] = scale * sum_kl conj(w_kl) S(i,j)_kl for the P*P
-    // blocks, dealt round-robin to the 4 waves; a wave's lanes split the q x q
+    // blocks, dealt round-robin to the waves; a wave's lanes split the q x q
     // entries (this lane: e = lane + 64 m, weight wv[m]) and reduce with DPP.
     // Optionally accumulates sum |S(i,j)_kl|^2 of the visited entries in *nr.
     // out[] is complete after the next block_sync.
     auto block_pass = [&](const float2 (&wv)[NL], float scale, float2* out, double* nr) {
-      for (int u = 0; u < (P * P + 3) / 4; ++u) {
-        const int ij = wave + 4 * u;
+      for (int u = 0; u < (P * P + kWideWaves - 1) / kWideWaves; ++u) {
+        const int ij = wave + kWideWaves * u;
         if (ij >= P * P) break;   // uniform per wave
         const int i = ij / P, j = ij - (ij / P) * P;
         const bool up = i <= j;
@@ -2095,7 +2119,9 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
           if (lane + 64 * m < QQ) {
-            const int e = lane + 64 * m, k = e / Q, l = e - k * Q;
+            const int e = lane + 64 * m;
+            int k = e / Q, l = e - (e / Q) * Q;
+            asm volatile("" : "+v"(k), "+v"(l));
             float2 sv = sS[base + (up ? k * QS + l : l * QS + k)];
             sv.y = up ? sv.y : -sv.y;
             acc = ccfma(wv[m], sv, acc);
@@ -2110,7 +2136,8 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     };
 
     // ------------------------------------------------ a4 init, ||R||_F = ||S||_F
-    float2 A[P * P];
+    // The current space factor A lives in LDS (sA, P x P): every lane reads
+    // it, as broadcasts, in the sweeps.
     double normR2;
     {
       float2 wv[NL];
@@ -2121,10 +2148,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       normR2 = block_sumd(nr, redd);   // its barriers also publish sAp
       float an = 0.f;
 #pragma unroll
-      for (int e = 0; e < P * P; ++e) {
-        A[e] = sAp[e];
-        an += cabs2(A[e]);
-      }
+      for (int e = 0; e < P * P; ++e) an += cabs2(sAp[e]);
       if (double(an) <= 1e-24 * normR2) {   // fallback: partial trace R vec(I_q)
 #pragma unroll
         for (int m = 0; m < NL; ++m) {
@@ -2134,9 +2158,8 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         block_sync();
         block_pass(wv, 1.f, sAp, nullptr);
         block_sync();
-#pragma unroll
-        for (int e = 0; e < P * P; ++e) A[e] = sAp[e];
       }
+      if (tid < P * P) sA[tid] = sAp[tid];
       block_sync();
     }
 
@@ -2149,13 +2172,13 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     for (int t = 0; t < NE; ++t) bv[t] = cz();
     EC ua[P];
 #pragma unroll
-    for (int i = 0; i < P; ++i) ua[i] = czero<EC>();
+    for (int i = 0; i < P; ++i) ua[i] = warm ? sUA[i * RAM] : czero<EC>();
 
     if (!zero && !bad) {
       double resid = 0.0;
       float anorm2 = 0.f;
 #pragma unroll
-      for (int e = 0; e < P * P; ++e) anorm2 += cabs2(A[e]);
+      for (int e = 0; e < P * P; ++e) anorm2 += cabs2(sA[e]);
       // One LR-Kron half-step pair: the new b = R^T conj(a) / ||a||^2
       // (lane-owned entries, all blocks), then the block pass R conj(b) /
       // ||b||^2 into sAp.  If RES also the residual of (A, b) by the expansion
@@ -2168,13 +2191,19 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         float bb = 0.f;
         if (res) {
 #pragma unroll
-          for (int e = 0; e < P * P; ++e) a2 = fma(double(A[e].x), double(A[e].x), fma(double(A[e].y), double(A[e].y), a2));
+          for (int e = 0; e < P * P; ++e) {
+            const float2 ae = sA[e];
+            a2 = fma(double(ae.x), double(ae.x), fma(double(ae.y), double(ae.y), a2));
+          }
         }
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
-          const int e = tid + 256 * t;
+          const int e = tid + kWideThreads * t;
           if (e < QQ) {
-            const int k = e / Q, l = e - (e / Q) * Q;
+            // opaque indices: the P^2 entry addresses are formed here, per
+            // sweep, not hoisted out of the iteration loop into registers
+            int k = e / Q, l = e - (e / Q) * Q;
+            asm volatile("" : "+v"(k), "+v"(l));
             float2 bn = cz();
             if (res) {
               double gx = 0.0, gy = 0.0;
@@ -2183,7 +2212,8 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
                   const float2 sv = Sget(i, j, k, l);
-                  const double ax = A[i * P + j].x, ay = A[i * P + j].y, sx = sv.x, sy = sv.y;
+                  const float2 aij = sA[i * P + j];
+                  const double ax = aij.x, ay = aij.y, sx = sv.x, sy = sv.y;
                   gx = fma(ax, sx, fma(ay, sy, gx));
                   gy = fma(ax, sy, fma(-ay, sx, gy));
                 }
@@ -2195,7 +2225,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
               for (int i = 0; i < P; ++i)
 #pragma unroll
-                for (int j = 0; j < P; ++j) bn = ccfma(A[i * P + j], Sget(i, j, k, l), bn);
+                for (int j = 0; j < P; ++j) bn = ccfma(sA[i * P + j], Sget(i, j, k, l), bn);
               bn = cscale(bn, ainv);
             }
             bv[t] = bn;
@@ -2215,8 +2245,14 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
           redd[wave] = rr;
         }
         block_sync();
-        const float bsum = (red[0] + red[1]) + (red[2] + red[3]);
-        if (res) resid = fmax(normR2 + ((redd[0] + redd[1]) + (redd[2] + redd[3])), 0.0);
+        float bsum = 0.f;
+        double rsum = 0.0;
+#pragma unroll
+        for (int i = 0; i < kWideWaves; ++i) {
+          bsum += red[i];
+          rsum += redd[i];
+        }
+        if (res) resid = fmax(normR2 + rsum, 0.0);
         float2 wv[NL];
 #pragma unroll
         for (int m = 0; m < NL; ++m) wv[m] = (lane + 64 * m < QQ) ? sB[lane + 64 * m] : cz();
@@ -2229,7 +2265,6 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
           const int i = tid / P, j = tid - (tid / P) * P;
           const EC h = cscale(cadd(cto<EC>(sAp[i * P + j]), cconj(cto<EC>(sAp[j * P + i]))), ES(0.5));
           sAh[tid] = h;
-          sA[tid] = tof(h);
         }
         block_sync();
         if (r_a == 1) {
@@ -2247,67 +2282,71 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
           for (int i = 0; i < P; ++i)
 #pragma unroll
             for (int j = 0; j < P; ++j) {
-              A[i * P + j] = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
-              anorm2 += cabs2(A[i * P + j]);
+              const float2 aij = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
+              anorm2 += cabs2(aij);
+              if (tid == i * P + j) sA[i * P + j] = aij;
             }
-          block_sync();   // sAh is rewritten by the next call
+          block_sync();   // publishes sA; sAh is rewritten by the next call
           return;
         }
-        // r_a > 1: every lane runs the same subspace iteration on Herm(A')
-        // (LDS), warm-started from the previous U_A
-        EC Vb[RAM][P];
-        if (!cold) {
+        // r_a > 1: wave 0 runs the subspace iteration with lane k holding row
+        // k of Herm(A') and of the basis (dot products by wave reductions),
+        // warm-started from the previous U_A; then Hs = U^H Herm(A') U
+        // (r_a x r_a) to LDS.  Every thread then forms A = U Hs U^H, with
+        // ||A||^2 = ||Hs||_F^2.  The sweep's reduction area is free here and
+        // holds the basis exchange and Hs.
+        EC* const sVs = reinterpret_cast<EC*>(red);   // [RAM][P] basis exchange
+        EC* const sHs = sVs + RAM * P;                 // [RAM][RAM]
+        if (wave == 0) {
+          const bool rowk = lane < P;
+          float2 mrow[P];
 #pragma unroll
-          for (int c = 0; c < RAM; ++c)
+          for (int j = 0; j < P; ++j) mrow[j] = tof(sAh[(rowk ? lane : 0) * P + j]);
+          EC va[RAM];
 #pragma unroll
-            for (int i = 0; i < P; ++i) Vb[c][i] = sUA[i * RAM + c];
-        }
-        uniform_subspace<RAM, P, EC>([&](int i, int j) { return sAh[i * P + j]; }, r_a, Vb, cold, 500,
-                                     PREC ? 1e-12 : 2e-6);
-        EC Hs[RAM][RAM];
+          for (int c = 0; c < RAM; ++c) va[c] = (!cold && rowk) ? sUA[lane * RAM + c] : czero<EC>();
+          group_subspace<RAM, 64, P, EC, true>(mrow, rowk, r_a, va, sVs, cold, 500, PREC ? 1e-12 : 2e-6);
+          small::lane_sync();
+          if (rowk) {
 #pragma unroll
-        for (int a = 0; a < RAM; ++a)
+            for (int c = 0; c < RAM; ++c)
+              if (c < r_a) sUA[lane * RAM + c] = va[c];
+          }
+          small::lane_sync();
+          // (Herm(A') U)[k][b] on lane k, then Hs[a][b] = sum_k conj(U[k][a]) (Herm(A') U)[k][b]
+          EC au[RAM];
 #pragma unroll
           for (int b = 0; b < RAM; ++b) {
-            EC sacc = czero<EC>();
-            if (a < r_a && b < r_a) {
+            au[b] = czero<EC>();
+            if (b < r_a && rowk) {
 #pragma unroll
-              for (int i = 0; i < P; ++i) {
-                EC t2 = czero<EC>();
+              for (int j = 0; j < P; ++j) au[b] = cfma(sAh[lane * P + j], sUA[j * RAM + b], au[b]);
+            }
+          }
 #pragma unroll
-                for (int j = 0; j < P; ++j) t2 = cfma(sAh[i * P + j], Vb[b][j], t2);
-                sacc = ccfma(Vb[a][i], t2, sacc);
+          for (int a2 = 0; a2 < RAM; ++a2)
+#pragma unroll
+            for (int b = 0; b < RAM; ++b)
+              if (a2 < r_a && b < r_a) {
+                const EC hs = gsum<64>(rowk ? ccfma(va[a2], au[b], czero<EC>()) : czero<EC>());
+                if (lane == 0) sHs[a2 * RAM + b] = hs;
               }
-            }
-            Hs[a][b] = sacc;
-          }
-        anorm2 = 0.f;
-#pragma unroll
-        for (int i = 0; i < P; ++i)
-#pragma unroll
-          for (int j = 0; j < P; ++j) {
-            EC sacc = czero<EC>();
-#pragma unroll
-            for (int a = 0; a < RAM; ++a) {
-              if (a >= r_a) continue;
-              EC t2 = czero<EC>();
-#pragma unroll
-              for (int b = 0; b < RAM; ++b)
-                if (b < r_a) t2 = cfma(Hs[a][b], cconj(Vb[b][j]), t2);
-              sacc = cfma(Vb[a][i], t2, sacc);
-            }
-            A[i * P + j] = tof(sacc);
-            anorm2 += cabs2(A[i * P + j]);
-          }
-        block_sync();   // every wave has read sUA and sAh
-        if (tid == 0) {
-#pragma unroll
-          for (int c = 0; c < RAM; ++c)
-#pragma unroll
-            for (int i = 0; i < P; ++i)
-              if (c < r_a) sUA[i * RAM + c] = Vb[c][i];
         }
         block_sync();
+        anorm2 = 0.f;
+        for (int a2 = 0; a2 < r_a; ++a2)
+          for (int b = 0; b < r_a; ++b) anorm2 += float(cabs2(sHs[a2 * RAM + b]));
+        if (tid < P * P) {
+          const int ai = tid / P, aj = tid - (tid / P) * P;
+          EC acc = czero<EC>();
+          for (int a2 = 0; a2 < r_a; ++a2) {
+            EC t2 = czero<EC>();
+            for (int b = 0; b < r_a; ++b) t2 = cfma(sHs[a2 * RAM + b], cconj(sUA[aj * RAM + b]), t2);
+            acc = cfma(sUA[ai * RAM + a2], t2, acc);
+          }
+          sA[tid] = tof(acc);
+        }
+        block_sync();   // publishes sA; the reduction area is free again
       };
       // sweep 0 has no residual; after sweep k >= 1 the stop rule looks at
       // eta_k (one call site per lambda keeps the code, and its registers, small)
@@ -2322,7 +2361,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
           if (stop) break;
           eta_prev = e;
         }
-        eig_a(k == 0);
+        eig_a(k == 0 && !warm);
         iters = k + 1;
       }
     }
@@ -2333,13 +2372,14 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       for (int i = 0; i < P; ++i) sUA[i * RAM] = ua[i];
     }
     chain = !bad;   // this S may seed the next pixel's
+    ua_ok = !zero && !bad;
     block_sync();
     // ------------------------------------------ enqueue for the batched tail
     // (sB holds the final b = R^T conj(a) / ||a||^2 of a finite pixel)
     float2* const hq = sHq + nq * QQ;
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
-      const int e = tid + 256 * t;
+      const int e = tid + kWideThreads * t;
       if (e < QQ) {
         const int k = e / Q, l = e - (e / Q) * Q;
         hq[e] = cscale(cadd(sB[k * Q + l], cconj(sB[l * Q + k])), 0.5f);
@@ -2369,7 +2409,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 }
 
 template <int P, int Q, int RBM, int MODE, int PREC, bool VAR = false>
-__global__ __launch_bounds__(256, 1) void kstap_wide_kernel(const KParams prm) {
+__global__ __launch_bounds__(kWideThreads, 1) void kstap_wide_kernel(const KParams prm) {
   __shared__ __attribute__((aligned(16))) char lds[WideLds<P, Q, RBM, PREC>::bytes];
   int64_t first, count;
   if (MODE == kModeRun) {
@@ -2412,12 +2452,13 @@ int launch_wide(int mode, const KParams& prm, hipStream_t stream) {
   int64_t grid = (mode == kModeRun) ? ((units + 7) / 8) * 8 : units;
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
   if (mode == kModeRun && has_variants(prm))
-    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeRun, PREC, true>), dim3(unsigned(grid)), dim3(256), 0,
+    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeRun, PREC, true>), dim3(unsigned(grid)), dim3(kWideThreads), 0,
                        stream, prm);
   else if (mode == kModeRun)
-    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeRun, PREC>), dim3(unsigned(grid)), dim3(256), 0, stream, prm);
+    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeRun, PREC>), dim3(unsigned(grid)), dim3(kWideThreads), 0, stream,
+                       prm);
   else
-    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeProbe, PREC>), dim3(unsigned(grid)), dim3(256), 0, stream,
+    hipLaunchKernelGGL((kstap_wide_kernel<P, Q, RBM, kModeProbe, PREC>), dim3(unsigned(grid)), dim3(kWideThreads), 0, stream,
                        prm);
   return hipGetLastError();
 }
