@@ -2106,32 +2106,45 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
     // entries (this lane: e = lane + 64 m, weight wv[m]) and reduce with DPP.
     // Optionally accumulates sum |S(i,j)_kl|^2 of the visited entries in *nr.
     // out[] is complete after the next block_sync.
+    // The wave's blocks are accumulated first and reduced together, so the
+    // DPP reduction chains of different blocks overlap.
     auto block_pass = [&](const float2 (&wv)[NL], float scale, float2* out, double* nr) {
-      for (int u = 0; u < (P * P + kWideWaves - 1) / kWideWaves; ++u) {
-        const int ij = wave + kWideWaves * u;
-        if (ij >= P * P) break;   // uniform per wave
-        const int i = ij / P, j = ij - (ij / P) * P;
-        const bool up = i <= j;
-        const int a = up ? i : j, b = up ? j : i;
-        const int base = (a * P - a * (a - 1) / 2 + (b - a)) * Q * QS;
-        float2 acc = cz();
-        double n2 = 0.0;   // exact squares of the FP32 entries, FP64 sums
+      constexpr int NU = (P * P + kWideWaves - 1) / kWideWaves;
+      float2 acc[NU];
+      double n2 = 0.0;   // exact squares of the FP32 entries, FP64 sums
 #pragma unroll
-        for (int m = 0; m < NL; ++m) {
-          if (lane + 64 * m < QQ) {
-            const int e = lane + 64 * m;
-            int k = e / Q, l = e - (e / Q) * Q;
-            asm volatile("" : "+v"(k), "+v"(l));
-            float2 sv = sS[base + (up ? k * QS + l : l * QS + k)];
-            sv.y = up ? sv.y : -sv.y;
-            acc = ccfma(wv[m], sv, acc);
-            if (nr) n2 = fma(double(sv.x), double(sv.x), fma(double(sv.y), double(sv.y), n2));
+      for (int u = 0; u < NU; ++u) {
+        acc[u] = cz();
+        const int ij = wave + kWideWaves * u;
+        if (ij < P * P) {   // uniform per wave
+          const int i = ij / P, j = ij - (ij / P) * P;
+          const bool up = i <= j;
+          const int a = up ? i : j, b = up ? j : i;
+          const int base = (a * P - a * (a - 1) / 2 + (b - a)) * Q * QS;
+#pragma unroll
+          for (int m = 0; m < NL; ++m) {
+            if (lane + 64 * m < QQ) {
+              const int e = lane + 64 * m;
+              int k = e / Q, l = e - (e / Q) * Q;
+              asm volatile("" : "+v"(k), "+v"(l));
+              float2 sv = sS[base + (up ? k * QS + l : l * QS + k)];
+              sv.y = up ? sv.y : -sv.y;
+              acc[u] = ccfma(wv[m], sv, acc[u]);
+              if (nr) n2 = fma(double(sv.x), double(sv.x), fma(double(sv.y), double(sv.y), n2));
+            }
           }
         }
-        if (nr) *nr += n2;
-        acc.x = wsum(acc.x);
-        acc.y = wsum(acc.y);
-        if (lane == 0) out[ij] = cscale(acc, scale);
+      }
+      if (nr) *nr += n2;
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        acc[u].x = wsum(acc[u].x);
+        acc[u].y = wsum(acc[u].y);
+      }
+#pragma unroll
+      for (int u = 0; u < NU; ++u) {
+        const int ij = wave + kWideWaves * u;
+        if (ij < P * P && lane == 0) out[ij] = cscale(acc[u], scale);
       }
     };
 
@@ -2206,26 +2219,41 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
             asm volatile("" : "+v"(k), "+v"(l));
             float2 bn = cz();
             if (res) {
-              double gx = 0.0, gy = 0.0;
+              // one partial sum per block row: P independent FMA chains
+              double px[P], py[P];
 #pragma unroll
-              for (int i = 0; i < P; ++i)
+              for (int i = 0; i < P; ++i) {
+                px[i] = 0.0;
+                py[i] = 0.0;
 #pragma unroll
                 for (int j = 0; j < P; ++j) {
                   const float2 sv = Sget(i, j, k, l);
                   const float2 aij = sA[i * P + j];
                   const double ax = aij.x, ay = aij.y, sx = sv.x, sy = sv.y;
-                  gx = fma(ax, sx, fma(ay, sy, gx));
-                  gy = fma(ax, sy, fma(-ay, sx, gy));
+                  px[i] = fma(ax, sx, fma(ay, sy, px[i]));
+                  py[i] = fma(ax, sy, fma(-ay, sx, py[i]));
                 }
+              }
+              double gx = 0.0, gy = 0.0;
+#pragma unroll
+              for (int i = 0; i < P; ++i) {
+                gx += px[i];
+                gy += py[i];
+              }
               const double bx = bv[t].x, by = bv[t].y;
               xr = fma(bx, gx, fma(by, gy, xr));
               b2 = fma(bx, bx, fma(by, by, b2));
               bn = make_float2(float(gx) * ainv, float(gy) * ainv);
             } else {
+              float2 pb[P];
 #pragma unroll
-              for (int i = 0; i < P; ++i)
+              for (int i = 0; i < P; ++i) {
+                pb[i] = cz();
 #pragma unroll
-                for (int j = 0; j < P; ++j) bn = ccfma(sA[i * P + j], Sget(i, j, k, l), bn);
+                for (int j = 0; j < P; ++j) pb[i] = ccfma(sA[i * P + j], Sget(i, j, k, l), pb[i]);
+              }
+#pragma unroll
+              for (int i = 0; i < P; ++i) bn = cadd(bn, pb[i]);
               bn = cscale(bn, ainv);
             }
             bv[t] = bn;
@@ -2268,25 +2296,35 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         }
         block_sync();
         if (r_a == 1) {
-          power_top<P, EC>([&](int i, int j) { return sAh[i * P + j]; }, ua, cold, 500, PREC ? 1e-12 : 2e-6);
-          ES lam = 0;
+          // wave 0 alone: the iteration is the same on every lane, so the
+          // other waves would only take SIMD issue slots from it
+          if (wave == 0) {
+            if constexpr (PREC == 0) {   // the factor in registers for the iteration (FP32 fits the budget)
+              EC mh[P * P];
 #pragma unroll
-          for (int i = 0; i < P; ++i) {
-            EC s = czero<EC>();
+              for (int e = 0; e < P * P; ++e) mh[e] = sAh[e];
+              power_top<P, EC>([&](int i, int j) { return mh[i * P + j]; }, ua, cold, 500, 2e-6);
+            } else {
+              power_top<P, EC>([&](int i, int j) { return sAh[i * P + j]; }, ua, cold, 500, 1e-12);
+            }
+            ES lam = 0;
 #pragma unroll
-            for (int j = 0; j < P; ++j) s = cfma(sAh[i * P + j], ua[j], s);
-            lam += ua[i].x * s.x + ua[i].y * s.y;
+            for (int i = 0; i < P; ++i) {
+              EC s = czero<EC>();
+#pragma unroll
+              for (int j = 0; j < P; ++j) s = cfma(sAh[i * P + j], ua[j], s);
+              lam += ua[i].x * s.x + ua[i].y * s.y;
+            }
+#pragma unroll
+            for (int i = 0; i < P; ++i)
+#pragma unroll
+              for (int j = 0; j < P; ++j)
+                if (lane == i * P + j) sA[i * P + j] = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
           }
+          block_sync();   // publishes sA; sAh is rewritten by the next call
           anorm2 = 0.f;
 #pragma unroll
-          for (int i = 0; i < P; ++i)
-#pragma unroll
-            for (int j = 0; j < P; ++j) {
-              const float2 aij = tof(cscale(cmul(ua[i], cconj(ua[j])), lam));
-              anorm2 += cabs2(aij);
-              if (tid == i * P + j) sA[i * P + j] = aij;
-            }
-          block_sync();   // publishes sA; sAh is rewritten by the next call
+          for (int e = 0; e < P * P; ++e) anorm2 += cabs2(sA[e]);
           return;
         }
         // r_a > 1: wave 0 runs the subspace iteration with lane k holding row
