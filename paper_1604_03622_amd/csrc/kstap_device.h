@@ -543,6 +543,14 @@ __device__ __forceinline__ void ssums_add(SSums<P>& ss, int I, int J, int row, i
 }
 
 // ------------------------------------------------------------ a2, FP32
+// Classes whose per-lane S element addresses do not fit in registers beside
+// the rest of the pixel state: there the tile row and column are made opaque
+// so that the addresses are formed where used, per pixel, instead of being
+// hoisted out of the pixel loop, spilled and reloaded.
+template <int P, int Q>
+constexpr bool kOpaqueStore = (P == 2 && Q == 32) || (P == 3 && Q == 12) || (P == 4 && Q == 8) ||
+                               (P == 4 && Q == 16) || (P == 6 && Q == 8);
+
 // S = (1/n) sum_m x_m x_m^H of one pixel on v_mfma_f32_16x16x4_f32, written
 // to LDS as the full Hermitian pq x pq matrix (row-major).
 template <int P, int Q>
@@ -644,7 +652,8 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
     // Im of a diagonal tile is P - P^T with P = Xi Xr^T: the raw P goes through
     // the scratch sP ([NB][16][16]) for the transposed element.
     const float inv_n = 1.f / float(n);
-    const int trow = 4 * (lane >> 4), tcol = lane & 15;
+    int trow = 4 * (lane >> 4), tcol = lane & 15;
+    if constexpr (kOpaqueStore<P, Q>) asm volatile("" : "+v"(trow), "+v"(tcol));
 #pragma unroll
     for (int I = 0; I < NB; ++I)
 #pragma unroll
@@ -690,7 +699,8 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
   constexpr int NT = NB * (NB + 1) / 2;
   constexpr int NO = NB * (NB - 1) / 2;
   const int lane = threadIdx.x;
-  const int trow = 4 * (lane >> 4), tcol = lane & 15;
+  int trow = 4 * (lane >> 4), tcol = lane & 15;
+  if constexpr (kOpaqueStore<P, Q>) asm volatile("" : "+v"(trow), "+v"(tcol));
   const float fn = float(n);
   f4 accR[NT], accI[NO > 0 ? NO : 1], accD[NB];
   {
