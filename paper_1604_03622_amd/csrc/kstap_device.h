@@ -524,21 +524,61 @@ struct SSums {
   float2 a0[P * P];
   float nr;
 };
+// off: the element is not on the diagonal of S.
 template <int P, int Q>
-__device__ __forceinline__ void ssums_add(SSums<P>& ss, int I, int J, int row, int col, float2 v) {
+__device__ __forceinline__ void ssums_add(SSums<P>& ss, int I, int J, bool off, float2 v) {
   if constexpr (Q % 16 == 0) {
     const int bi = (16 * I) / Q, bj = (16 * J) / Q;   // constants once the tile loops unroll
     const float m = cabs2(v);
     if (bi != bj) {
       ss.a0[bi * P + bj] = cadd(ss.a0[bi * P + bj], v);
       ss.nr += 2.f * m;
-    } else if (row != col) {
+    } else if (off) {
       ss.a0[bi * P + bi].x += 2.f * v.x;   // v + conj(v)
       ss.nr += 2.f * m;
     } else {
       ss.a0[bi * P + bi] = cadd(ss.a0[bi * P + bi], v);
       ss.nr += m;
     }
+  }
+}
+
+// Element (tr, tc) of the 16 x 16 MFMA tile (I, J), I <= J: row 16 I + tr,
+// column 16 J + tc of the stacked matrix, 0 <= tr, tc < 16.  Written so that
+// what the tile indices fix (the tile lies inside the matrix, above its
+// diagonal, inside one q x q block) folds once the tile loops unroll: only
+// diagonal and ragged tiles test their lanes, and no per-lane predicate of
+// an off-diagonal tile is kept live across the pixel loop.
+template <int P, int Q>
+__device__ __forceinline__ bool tile_in(int I, int J, int tr, int tc) {
+  constexpr int PQ = P * Q;
+  return (16 * I + 16 <= PQ || 16 * I + tr < PQ) && (16 * J + 16 <= PQ || 16 * J + tc < PQ);
+}
+// inside the matrix and on or above its diagonal (row == col iff I == J and
+// tr == tc, since |tc - tr| < 16)
+template <int P, int Q>
+__device__ __forceinline__ bool tile_keep(int I, int J, int tr, int tc) {
+  return tile_in<P, Q>(I, J, tr, tc) && (J > I || tr <= tc);
+}
+template <int P, int Q>
+__device__ __forceinline__ float2 tile_get(const float2* sS, int I, int J, int tr, int tc) {
+  if constexpr (Q % 16 == 0) {   // the tile lies in upper block ((16 I) / q, (16 J) / q)
+    return sS[sblk<P, Q>((16 * I) / Q, (16 * J) / Q) + ((16 * I) % Q + tr) * (Q + 1) + (16 * J) % Q + tc];
+  } else {
+    const int row = 16 * I + tr, col = 16 * J + tc;
+    return sget<P, Q>(sS, row / Q, col / Q, row % Q, col % Q);
+  }
+}
+// sput of a tile element that tile_keep accepts
+template <int P, int Q>
+__device__ __forceinline__ void tile_put(float2* sS, int I, int J, int tr, int tc, float2 v) {
+  if constexpr (Q % 16 == 0) {
+    const int bi = (16 * I) / Q, bj = (16 * J) / Q;
+    const int ka = (16 * I) % Q + tr, kb = (16 * J) % Q + tc;
+    sS[sblk<P, Q>(bi, bj) + ka * (Q + 1) + kb] = v;
+    if (bi == bj) sS[sblk<P, Q>(bi, bj) + kb * (Q + 1) + ka] = make_float2(v.x, -v.y);
+  } else {
+    sput<P, Q>(sS, 16 * I + tr, 16 * J + tc, v);
   }
 }
 
@@ -667,13 +707,13 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
         for (int J = I; J < NB; ++J) {
 #pragma unroll
           for (int q4 = 0; q4 < 4; ++q4) {
-            const int row = 16 * I + trow + q4, col = 16 * J + tcol;
-            if (row < PQ && col < PQ && row <= col) {
+            const int tr = trow + q4;
+            if (tile_keep<P, Q>(I, J, tr, tcol)) {
               const float re = accR[t][q4] * inv_n;
               const float im = (J > I) ? accI[u][q4] * inv_n
-                                       : (accD[I][q4] - sP[(I * 16 + tcol) * 16 + trow + q4]) * inv_n;
-              sput<P, Q>(sS, row, col, make_float2(re, im));
-              ssums_add<P, Q>(ss, I, J, row, col, make_float2(re, im));
+                                       : (accD[I][q4] - sP[(I * 16 + tcol) * 16 + tr]) * inv_n;
+              tile_put<P, Q>(sS, I, J, tr, tcol, make_float2(re, im));
+              ssums_add<P, Q>(ss, I, J, I != J || tr != tcol, make_float2(re, im));
             }
           }
           if (J > I) ++u;
@@ -711,9 +751,9 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
       for (int J = I; J < NB; ++J) {
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
-          const int row = 16 * I + trow + q4, col = 16 * J + tcol;
+          const int tr = trow + q4;
           float2 v = make_float2(0.f, 0.f);
-          if (row < PQ && col < PQ) v = sget<P, Q>(sS, row / Q, col / Q, row % Q, col % Q);
+          if (tile_in<P, Q>(I, J, tr, tcol)) v = tile_get<P, Q>(sS, I, J, tr, tcol);
           accR[t][q4] = v.x * fn;
           if (J > I) accI[u][q4] = v.y * fn;
           else accD[I][q4] = v.y * fn;
@@ -774,11 +814,11 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
       for (int J = I; J < NB; ++J) {
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
-          const int row = 16 * I + trow + q4, col = 16 * J + tcol;
-          if (row < PQ && col < PQ && row <= col) {
+          const int tr = trow + q4;
+          if (tile_keep<P, Q>(I, J, tr, tcol)) {
             const float2 v = make_float2(accR[t][q4] * inv_n, ((J > I) ? accI[u][q4] : accD[I][q4]) * inv_n);
-            sput<P, Q>(sS, row, col, v);
-            ssums_add<P, Q>(ss, I, J, row, col, v);
+            tile_put<P, Q>(sS, I, J, tr, tcol, v);
+            ssums_add<P, Q>(ss, I, J, I != J || tr != tcol, v);
           }
         }
         if (J > I) ++u;
@@ -927,11 +967,11 @@ __device__ __forceinline__ void scm_bf16x3(const uint32_t* hwin, const uint32_t*
     for (int J = I; J < NB; ++J, ++t)
 #pragma unroll
       for (int q4 = 0; q4 < 4; ++q4) {
-        const int row = 16 * I + trow + q4, col = 16 * J + tcol;
-        if (row < PQ && col < PQ && row <= col) {
+        const int tr = trow + q4;
+        if (tile_keep<P, Q>(I, J, tr, tcol)) {
           const float2 v = make_float2(accR[t][q4] * inv_n, accI[t][q4] * inv_n);
-          sput<P, Q>(sS, row, col, v);
-          ssums_add<P, Q>(ss, I, J, row, col, v);
+          tile_put<P, Q>(sS, I, J, tr, tcol, v);
+          ssums_add<P, Q>(ss, I, J, I != J || tr != tcol, v);
         }
       }
   wave_sync();
@@ -1455,7 +1495,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 #pragma unroll
         for (int t = 0; t < NE; ++t) {
           const int e = lane + 64 * t;
-          if (e < QQ) {
+          if (QQ % 64 == 0 || e < QQ) {
             const int k = e / Q, l = e - (e / Q) * Q;
             float2 s[P * P];
 #pragma unroll
@@ -1642,7 +1682,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = lane + 64 * t;
-      if (e < QQ) sBT[e] = bv[t];   // B[k][l] at k*q + l
+      if (QQ % 64 == 0 || e < QQ) sBT[e] = bv[t];   // B[k][l] at k*q + l
     }
     wave_sync();
     if (tg == nq && tk < Q) {
