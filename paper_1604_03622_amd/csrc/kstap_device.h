@@ -583,13 +583,14 @@ __device__ __forceinline__ void tile_put(float2* sS, int I, int J, int tr, int t
 }
 
 // ------------------------------------------------------------ a2, FP32
-// Classes whose per-lane S element addresses do not fit in registers beside
-// the rest of the pixel state: there the tile row and column are made opaque
-// so that the addresses are formed where used, per pixel, instead of being
-// hoisted out of the pixel loop, spilled and reloaded.
+// Classes where the tile row and column are made opaque, so that the S
+// element addresses and the diagonal tiles' lane masks are formed where used,
+// per pixel, instead of being hoisted out of the pixel loop, spilled and
+// reloaded: q a multiple of 16 (one base address per lane, the tile offsets
+// are constants), and the classes whose addresses do not fit in registers
+// beside the rest of the pixel state.
 template <int P, int Q>
-constexpr bool kOpaqueStore = (P == 2 && Q == 32) || (P == 3 && Q == 12) || (P == 4 && Q == 8) ||
-                               (P == 4 && Q == 16) || (P == 6 && Q == 8);
+constexpr bool kOpaqueStore = Q % 16 == 0 || (P == 3 && Q == 12) || (P == 4 && Q == 8) || (P == 6 && Q == 8);
 
 // S = (1/n) sum_m x_m x_m^H of one pixel on v_mfma_f32_16x16x4_f32, written
 // to LDS as the full Hermitian pq x pq matrix (row-major).
