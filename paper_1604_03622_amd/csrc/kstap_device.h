@@ -83,6 +83,14 @@ __device__ __forceinline__ float2 tof(float2 a) { return a; }
 __device__ __forceinline__ float2 tof(double2 a) { return make_float2(float(a.x), float(a.y)); }
 __device__ __forceinline__ float xsqrt(float a) { return sqrtf(a); }
 __device__ __forceinline__ double xsqrt(double a) { return sqrt(a); }
+// Scale factors that normalise an iterate or divide by a uniform norm: the
+// hardware reciprocal (square root) in FP32, within one ulp, where the scale
+// only has to be consistent (the next step renormalises, a statistic or a
+// subspace does not depend on it); exact in FP64.  The argument is a normal
+// positive number.
+__device__ __forceinline__ float xrsqrt(float a) { return __builtin_amdgcn_rsqf(a); }
+__device__ __forceinline__ double xrsqrt(double a) { return 1.0 / sqrt(a); }
+__device__ __forceinline__ float xrcp(float a) { return __builtin_amdgcn_rcpf(a); }
 __device__ __forceinline__ float xmax(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ double xmax(double a, double b) { return fmax(a, b); }
 
@@ -211,7 +219,7 @@ __device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
       }
     }
     const S nn = gsum<QP>(act ? cabs2(w[c]) : S(0));
-    const S inv = S(1) / xsqrt(xmax(nn, tiny<S>()));
+    const S inv = xrsqrt(xmax(nn, tiny<S>()));
     w[c] = act ? cscale(w[c], inv) : czero<C>();
   }
 }
@@ -390,7 +398,7 @@ __device__ __forceinline__ int uniform_subspace(MF M, int r, C (&V)[RM][P], bool
       S nn = 0;
 #pragma unroll
       for (int i = 0; i < P; ++i) nn += cabs2(Wm[c][i]);
-      const S inv = S(1) / xsqrt(xmax(nn, tiny<S>()));
+      const S inv = xrsqrt(xmax(nn, tiny<S>()));
 #pragma unroll
       for (int i = 0; i < P; ++i) Wm[c][i] = cscale(Wm[c][i], inv);
     }
@@ -434,7 +442,7 @@ __device__ __forceinline__ void power_top(MF M, C (&u)[P], bool cold, int max_st
     S nn = 0;
 #pragma unroll
     for (int i = 0; i < P; ++i) nn += cabs2(u[i]);
-    const S inv = nn > S(0) ? S(1) / xsqrt(nn) : S(0);
+    const S inv = nn > S(0) ? xrsqrt(xmax(nn, tiny<S>())) : S(0);
 #pragma unroll
     for (int i = 0; i < P; ++i) u[i] = cscale(u[i], inv);
   }
@@ -454,7 +462,7 @@ __device__ __forceinline__ void power_top(MF M, C (&u)[P], bool cold, int max_st
 #pragma unroll
     for (int i = 0; i < P; ++i) rn += cabs2(csub(w[i], cscale(u[i], lam)));
     if (!(wn > S(0))) break;
-    const S inv = S(1) / xsqrt(wn);
+    const S inv = xrsqrt(xmax(wn, tiny<S>()));
 #pragma unroll
     for (int i = 0; i < P; ++i) u[i] = cscale(w[i], inv);
     if (rn <= S(tol * tol) * wn) break;
@@ -1487,7 +1495,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       // one sweep over S: residual of (A, bv) if RES, then the new b and the
       // partial sums of R conj(b)
       auto sweep = [&](bool res) __attribute__((always_inline)) {
-        const float ainv = 1.f / anorm2;
+        const float ainv = xrcp(anorm2);
         float2 ap[P * P];
 #pragma unroll
         for (int e = 0; e < P * P; ++e) ap[e] = cz();
@@ -1522,7 +1530,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
           }
         }
         bn2 = wsum(bb);
-        const float binv = 1.f / bn2;
+        const float binv = xrcp(bn2);
 #pragma unroll
         for (int ij = 0; ij < P * P; ++ij) Ap[ij] = cscale(wsum(ap[ij]), binv);
         if (res) resid = wsumd(rr);
@@ -2250,7 +2258,7 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
       // FP64 from the FP32 entries (each product exact), so the expansion
       // keeps the residual where it is small.
       auto sweep = [&](bool res) __attribute__((always_inline)) {
-        const float ainv = 1.f / anorm2;
+        const float ainv = xrcp(anorm2);
         double rr = 0.0, xr = 0.0, b2 = 0.0, a2 = 0.0;
         float bb = 0.f;
         if (res) {
