@@ -227,7 +227,8 @@ __device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
 // Top-r invariant subspace of one Hermitian D x D matrix per lane group by
 // subspace iteration.  Lane k of a group holds row k of the matrix (mrow) and
 // row k of the orthonormal basis v (CGS2 orthonormalisation).  `cold` starts from M * Omega (Omega a
-// fixed generic block); otherwise v is the warm start.  A group has converged
+// fixed generic block), except in the groups whose lanes set `keep`, which
+// start from v; otherwise v is the warm start of every group.  A group has converged
 // when ||M V - V (V^H M V)||_F <= tol ||M V||_F for the basis entering a step;
 // that step's orthonormalised M V is kept and the group's basis is frozen.
 // The loop runs until every group has converged or max_steps; each group's
@@ -236,7 +237,7 @@ __device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
 // others that run their own solves, so it synchronises only its own lanes.
 template <int RM, int QP, int D, typename C, bool WAVE_LOCAL = false>
 __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_ok, int r, C (&v)[RM],
-                                              C* sV, bool cold, int max_steps, double tol) {
+                                              C* sV, bool cold, int max_steps, double tol, bool keep = false) {
   using S = decltype(C{}.x);
   constexpr int G = 64 / QP;
   const int lane = threadIdx.x & 63, g = lane / QP, k = lane % QP;   // lane within its wavefront
@@ -247,9 +248,12 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
     int kk = k;
     if constexpr (sizeof(S) == 8) asm volatile("" : "+v"(kk));
 #pragma unroll
-    for (int c = 0; c < RM; ++c) v[c] = (row_ok && c < r) ? cto<C>(omega(kk, c)) : czero<C>();
+    for (int c = 0; c < RM; ++c)
+      if (!keep) v[c] = (row_ok && c < r) ? cto<C>(omega(kk, c)) : czero<C>();
   }
-  bool tested = !cold;
+  // a warm start is tested on the first step (a cold group tested there
+  // does not pass: M Omega leaves the span of Omega)
+  bool tested = !cold || __ballot(keep) != 0;
   bool done = false;
   int step = 0;
   while (true) {
@@ -1023,11 +1027,13 @@ __device__ __forceinline__ void write_outside(const KParams& prm, int64_t idx) {
 // index, a flag (0 ok, 1 zero covariance, 2 non-finite), eta, the iteration
 // count and U_A (p x RAM).  Writes T (and D, or the probe outputs).
 // WAVE_LOCAL: other wavefronts of the workgroup run their own tails.
+// vb: this lane's row of its slot's basis; on entry the warm start of the
+// slots whose lanes set `keep` (the others start cold), on return the basis.
 template <int P, int Q, int RBM, int MODE, typename EC, bool WAVE_LOCAL, bool VAR>
 __device__ __forceinline__ void tail_batch(const KParams& prm, const float2 (&Bq)[Q], int slot, int nfill,
                                            const int* sQflag, const int64_t* sQidx, const float* sQeta,
                                            const int* sQit, const EC (*sQUA)[P * ((P < kMaxRA) ? P : kMaxRA)],
-                                           EC* scratch, double tol) {
+                                           EC* scratch, double tol, EC (&vb)[RBM], bool keep, bool& vb_ok) {
   using ES = decltype(EC{}.x);
   constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
   constexpr int QP = Groups<Q>::QP;
@@ -1038,11 +1044,13 @@ __device__ __forceinline__ void tail_batch(const KParams& prm, const float2 (&Bq
   const bool rok = slot_ok && tk < Q;
   const int flag = slot_ok ? sQflag[slot] : 1;
   const int64_t pidx = slot_ok ? sQidx[slot] : 0;
-  EC vb[RBM];
+  keep = keep && rok && flag == 0;
 #pragma unroll
-  for (int c = 0; c < RBM; ++c) vb[c] = czero<EC>();
+  for (int c = 0; c < RBM; ++c)
+    if (!keep) vb[c] = czero<EC>();
   if (r_b > 0)
-    group_subspace<RBM, QP, Q, EC, WAVE_LOCAL>(Bq, rok && flag == 0, r_b, vb, scratch, true, 200, tol);
+    group_subspace<RBM, QP, Q, EC, WAVE_LOCAL>(Bq, rok && flag == 0, r_b, vb, scratch, true, 200, tol, keep);
+  vb_ok = rok && flag == 0;
   // statistic
   int pr, pc;
   if (MODE == kModeRun) {
@@ -1343,9 +1351,33 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
   int nq = 0;
 
   // ------------------------------------------------ a6 + a8 for G pixels
+  // FP32 run mode: the queue holds the pixels of one sliding-window chain at
+  // a time, and every batch of a chain but its first starts each slot from
+  // the converged time-factor subspace of the previous batch's slot G-1-g,
+  // its nearest pixel in the snake order of a unit (directly above it for
+  // q = 16).  Like the sliding window, the choice depends only on the chain,
+  // so the results are the same for every decomposition of the frame.
+  constexpr bool kWarmTail = PREC == 0 && MODE == kModeRun;
+  EC vbw[RBM];   // lane (g, k): row k of the basis that starts slot g
+#pragma unroll
+  for (int c = 0; c < RBM; ++c) vbw[c] = czero<EC>();
+  bool vbw_ok = false;
+  int64_t qchain = -1, bchain = -2;   // chain of the queued pixels, of the last batch
   auto tail = [&](int nfill) __attribute__((always_inline)) {
+    const bool keep = kWarmTail && bchain == qchain && vbw_ok;
+    bool ok;
     tail_batch<P, Q, RBM, MODE, EC, false, VAR>(prm, Bq, tg, nfill, sQflag, sQidx, sQeta, sQit, sQUA, tail_scratch,
-                                                PREC ? 1e-10 : 2e-6);
+                                                PREC ? 1e-10 : 2e-6, vbw, keep, ok);
+    if constexpr (kWarmTail) {
+      bchain = qchain;
+      const int src = (G - 1 - tg) * QP + tk;
+#pragma unroll
+      for (int c = 0; c < RBM; ++c) {
+        vbw[c].x = __shfl(vbw[c].x, src);
+        vbw[c].y = __shfl(vbw[c].y, src);
+      }
+      vbw_ok = __shfl(int(ok), src) != 0;
+    }
   };
 
   // Sliding window (run mode, FP32 path): every position of a chain but the
@@ -1687,7 +1719,24 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     ua_ok = !zero && !bad;
 
     // ------------------------------------------ enqueue for the batched tail
+    // A full queue, or (warm tail) one that holds another chain's pixels,
+    // runs its batch here, before this pixel joins: the queued pixels wait in
+    // Bq and their own LDS slots, which this pixel's work does not touch, and
+    // the tail is inlined at one place in the loop.
     wave_sync();   // S is dead from here on
+    {
+      bool flush = nq == G;
+      int64_t cid = 0;
+      if constexpr (kWarmTail) {
+        cid = (first + it) / kChainNarrow;
+        flush = flush || (nq > 0 && cid != qchain);
+      }
+      if (flush) {
+        tail(nq);
+        nq = 0;
+      }
+      if constexpr (kWarmTail) qchain = cid;
+    }
 #pragma unroll
     for (int t = 0; t < NE; ++t) {
       const int e = lane + 64 * t;
@@ -1706,10 +1755,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     }
     if (lane < P * RAM) sQUA[nq][lane] = (zero || bad) ? czero<EC>() : sUA[lane];
     wave_sync();
-    if (++nq == G) {
-      tail(G);
-      nq = 0;
-    }
+    ++nq;
   }
   if (nq > 0) tail(nq);
 }
@@ -1950,8 +1996,10 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
 #pragma unroll
       for (int l = 0; l < Q; ++l) Bq[l] = own ? cconj(sHq[(slot < nfill ? slot : 0) * QQ + l * Q + tk]) : cz();
       EC* const scr = reinterpret_cast<EC*>(stage) + wave * (RBM * Q * G);
+      EC vb[RBM];
+      bool vb_ok;
       tail_batch<P, Q, RBM, MODE, EC, true, VAR>(prm, Bq, slot, nfill, sQflag, sQidx, sQeta, sQit, sQUA, scr,
-                                                 PREC ? 1e-10 : 2e-6);
+                                                 PREC ? 1e-10 : 2e-6, vb, false, vb_ok);
     }
     block_sync();
   };
