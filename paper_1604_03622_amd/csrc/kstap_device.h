@@ -740,8 +740,12 @@ __device__ __forceinline__ void scm_fp32(const float2* xwin, int64_t plane, uint
 // Sliding-window update of S (FP32): from the previous pixel's S (in LDS),
 // n S += sum over entering vectors x x^H - sum over leaving ones.  sAdd /
 // sRem: byte offsets (kOut past nadd / nrem and for 8 entries beyond).
-// Diagonal tiles take both Im products here (no transpose through LDS), so
-// the reloaded antisymmetric part stays exact.
+// Up to three 16-row blocks (where registers allow a third accumulator per
+// tile), every tile takes three real products per chunk instead of four:
+// with P1 = Xr Xr^T, P2 = Xi Xi^T and P3 = (Xr + Xi)(Xr - Xi)^T, Re S =
+// P1 + P2 and Im S = P3 - P1 + P2, and the diagonal of S is stored real.
+// Larger classes take Re and Im of every tile with two products each (no
+// transpose through LDS).
 template <int P, int Q>
 __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane, uint32_t rec,
                                                const uint32_t* sAdd, int nadd, const uint32_t* sRem, int nrem,
@@ -755,7 +759,11 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
   int trow = 4 * (lane >> 4), tcol = lane & 15;
   if constexpr (kOpaqueStore<P, Q>) asm volatile("" : "+v"(trow), "+v"(tcol));
   const float fn = float(n);
-  f4 accR[NT], accI[NO > 0 ? NO : 1], accD[NB];
+  constexpr bool K3 = NB <= 3;
+  // accR: Re (P1 in the three-product form); accI / accD: Im of the
+  // off-diagonal / diagonal tiles (four-product form); p2, p3: P2 and P3
+  f4 accR[NT], accI[(K3 || NO == 0) ? 1 : NO], accD[K3 ? 1 : NB];
+  f4 p2[K3 ? NT : 1], p3[K3 ? NT : 1];
   {
     int t = 0, u = 0;
 #pragma unroll
@@ -768,8 +776,13 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
           float2 v = make_float2(0.f, 0.f);
           if (tile_in<P, Q>(I, J, tr, tcol)) v = tile_get<P, Q>(sS, I, J, tr, tcol);
           accR[t][q4] = v.x * fn;
-          if (J > I) accI[u][q4] = v.y * fn;
-          else accD[I][q4] = v.y * fn;
+          if constexpr (K3) {
+            p2[t][q4] = 0.f;
+            p3[t][q4] = (v.x + v.y) * fn;
+          } else {
+            if (J > I) accI[u][q4] = v.y * fn;
+            else accD[I][q4] = v.y * fn;
+          }
         }
         if (J > I) ++u;
         ++t;
@@ -789,6 +802,28 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
       float2 v[NB];
 #pragma unroll
       for (int I = 0; I < NB; ++I) v[I] = bload(rs[I], loff[I] + off);
+      if constexpr (K3) {
+        float xr[NB], xi[NB], a1[NB], a2[NB], a3[NB], b3[NB];
+#pragma unroll
+        for (int I = 0; I < NB; ++I) {
+          xr[I] = v[I].x;
+          xi[I] = v[I].y;
+          a1[I] = sg * v[I].x;
+          a2[I] = sg * v[I].y;
+          a3[I] = sg * (v[I].x + v[I].y);
+          b3[I] = v[I].x - v[I].y;
+        }
+        int t = 0;
+#pragma unroll
+        for (int I = 0; I < NB; ++I)
+#pragma unroll
+          for (int J = I; J < NB; ++J, ++t) {
+            accR[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[I], xr[J], accR[t], 0, 0, 0);
+            p2[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[I], xi[J], p2[t], 0, 0, 0);
+            p3[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a3[I], b3[J], p3[t], 0, 0, 0);
+          }
+        continue;
+      }
       float xr[NB], xi[NB], sxr[NB], sxi[NB], nsxr[NB];
 #pragma unroll
       for (int I = 0; I < NB; ++I) {
@@ -829,7 +864,13 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
         for (int q4 = 0; q4 < 4; ++q4) {
           const int tr = trow + q4;
           if (tile_keep<P, Q>(I, J, tr, tcol)) {
-            const float2 v = make_float2(accR[t][q4] * inv_n, ((J > I) ? accI[u][q4] : accD[I][q4]) * inv_n);
+            float2 v;
+            if constexpr (K3) {
+              v.x = (accR[t][q4] + p2[t][q4]) * inv_n;
+              v.y = (I == J && tr == tcol) ? 0.f : ((p3[t][q4] - accR[t][q4]) + p2[t][q4]) * inv_n;
+            } else {
+              v = make_float2(accR[t][q4] * inv_n, ((J > I) ? accI[u][q4] : accD[I][q4]) * inv_n);
+            }
             tile_put<P, Q>(sS, I, J, tr, tcol, v);
             ssums_add<P, Q>(ss, I, J, I != J || tr != tcol, v);
           }
