@@ -114,6 +114,46 @@ __device__ __forceinline__ float wsum(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 __device__ __forceinline__ float2 wsum(float2 v) { return make_float2(wsum(v.x), wsum(v.y)); }
+// Sums over the 64 lanes of N values at once (N a multiple of 4), each
+// returned as a uniform value.  v_permlane32_swap exchanges the upper half of
+// value 2m with the lower half of value 2m + 1, so one add leaves value 2m
+// summed over lanes l and l + 32 in lanes 0-31 and value 2m + 1 in lanes
+// 32-63; v_permlane16_swap does the same between 16-lane rows, which leaves
+// four values per register, one per row (rows 0-3: values 4m, 4m + 2,
+// 4m + 1, 4m + 3), and four DPP steps finish every row.  About 3.5
+// instructions per value instead of the 7 of wsum.  The compiler folds the
+// sum of a swap's two results into twice its first result unless the results
+// pass through an empty asm first (swap_sum).
+__device__ __forceinline__ float swap_sum(unsigned r0, unsigned r1) {
+  asm volatile("" : "+v"(r0), "+v"(r1));
+  return __builtin_bit_cast(float, r0) + __builtin_bit_cast(float, r1);
+}
+template <int N>
+__device__ __forceinline__ void wsum_n(float (&v)[N]) {
+  static_assert(N % 4 == 0, "wsum_n sums a multiple of four values");
+  float w[N / 2];
+#pragma unroll
+  for (int m = 0; m < N / 2; ++m) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__builtin_bit_cast(unsigned, v[2 * m]),
+                                                    __builtin_bit_cast(unsigned, v[2 * m + 1]), false, false);
+    w[m] = swap_sum(r[0], r[1]);
+  }
+#pragma unroll
+  for (int m = 0; m < N / 4; ++m) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__builtin_bit_cast(unsigned, w[2 * m]),
+                                                    __builtin_bit_cast(unsigned, w[2 * m + 1]), false, false);
+    float x = swap_sum(r[0], r[1]);
+    x += dpp<0xB1, 0xF>(x);    // quad_perm [1,0,3,2]
+    x += dpp<0x4E, 0xF>(x);    // quad_perm [2,3,0,1]
+    x += dpp<0x141, 0xF>(x);   // row_half_mirror
+    x += dpp<0x140, 0xF>(x);   // row_mirror: every lane holds its row's sum
+    const int xi = __builtin_bit_cast(int, x);
+    v[4 * m] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 0));
+    v[4 * m + 2] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 16));
+    v[4 * m + 1] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 32));
+    v[4 * m + 3] = __builtin_bit_cast(float, __builtin_amdgcn_readlane(xi, 48));
+  }
+}
 template <int CTRL, int ROWS>
 __device__ __forceinline__ double dppd(double v) {
   const int2 i = __builtin_bit_cast(int2, v);
@@ -1492,13 +1532,32 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
       float2 a0[P * P];
       if constexpr (kSums) {
         normR2 = wsumd(double(ss.nr));
+        // the upper block sums in one multi-value reduction
+        constexpr int NU = P * (P + 1) / 2, NS = (2 * NU + 3) / 4 * 4;
+        float sums[NS];
+        {
+          int e = 0;
 #pragma unroll
-        for (int i = 0; i < P; ++i)
+          for (int i = 0; i < P; ++i)
 #pragma unroll
-          for (int j = i; j < P; ++j) {
-            a0[i * P + j] = cscale(wsum(ss.a0[i * P + j]), 1.f / float(QQ));
-            if (j > i) a0[j * P + i] = cconj(a0[i * P + j]);
-          }
+            for (int j = i; j < P; ++j, e += 2) {
+              sums[e] = ss.a0[i * P + j].x;
+              sums[e + 1] = ss.a0[i * P + j].y;
+            }
+#pragma unroll
+          for (int f = 2 * NU; f < NS; ++f) sums[f] = 0.f;
+        }
+        wsum_n<NS>(sums);
+        {
+          int e = 0;
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+#pragma unroll
+            for (int j = i; j < P; ++j, e += 2) {
+              a0[i * P + j] = cscale(make_float2(sums[e], sums[e + 1]), 1.f / float(QQ));
+              if (j > i) a0[j * P + i] = cconj(a0[i * P + j]);
+            }
+        }
       } else {
 #pragma unroll
         for (int e = 0; e < P * P; ++e) a0[e] = cz();
@@ -1602,10 +1661,21 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
             bv[t] = cz();
           }
         }
-        bn2 = wsum(bb);
+        // the 2 p^2 sums of R conj(b) and ||b||^2 in one multi-value reduction
+        constexpr int NS = (2 * P * P + 1 + 3) / 4 * 4;
+        float sums[NS];
+#pragma unroll
+        for (int ij = 0; ij < P * P; ++ij) {
+          sums[2 * ij] = ap[ij].x;
+          sums[2 * ij + 1] = ap[ij].y;
+        }
+#pragma unroll
+        for (int e = 2 * P * P; e < NS; ++e) sums[e] = (e == 2 * P * P) ? bb : 0.f;
+        wsum_n<NS>(sums);
+        bn2 = sums[2 * P * P];
         const float binv = xrcp(bn2);
 #pragma unroll
-        for (int ij = 0; ij < P * P; ++ij) Ap[ij] = cscale(wsum(ap[ij]), binv);
+        for (int ij = 0; ij < P * P; ++ij) Ap[ij] = cscale(make_float2(sums[2 * ij], sums[2 * ij + 1]), binv);
         if (res) resid = wsumd(rr);
       };
 
