@@ -1578,8 +1578,13 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
           }
         }
         normR2 = wsumd(double(nr));
+        constexpr int NS = (2 * P * P + 3) / 4 * 4;
+        float sums[NS];
 #pragma unroll
-        for (int e = 0; e < P * P; ++e) a0[e] = cscale(wsum(a0[e]), 1.f / float(QQ));
+        for (int f = 0; f < NS; ++f) sums[f] = (f < 2 * P * P) ? ((f & 1) ? a0[f / 2].y : a0[f / 2].x) : 0.f;
+        wsum_n<NS>(sums);
+#pragma unroll
+        for (int e = 0; e < P * P; ++e) a0[e] = cscale(make_float2(sums[2 * e], sums[2 * e + 1]), 1.f / float(QQ));
       }
       float an = 0.f;
 #pragma unroll
@@ -2354,10 +2359,14 @@ __device__ __forceinline__ void run_pixels_wide(const KParams& prm, int64_t firs
         }
       }
       if (nr) *nr += n2;
+      {
+        constexpr int NS = (2 * NU + 3) / 4 * 4;
+        float sums[NS];
 #pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        acc[u].x = wsum(acc[u].x);
-        acc[u].y = wsum(acc[u].y);
+        for (int f = 0; f < NS; ++f) sums[f] = (f < 2 * NU) ? ((f & 1) ? acc[f / 2].y : acc[f / 2].x) : 0.f;
+        wsum_n<NS>(sums);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) acc[u] = make_float2(sums[2 * u], sums[2 * u + 1]);
       }
 #pragma unroll
       for (int u = 0; u < NU; ++u) {
