@@ -268,7 +268,8 @@ __device__ __forceinline__ void orth_cgs2(C (&w)[RM], int r, bool act) {
 // subspace iteration.  Lane k of a group holds row k of the matrix (mrow) and
 // row k of the orthonormal basis v (CGS2 orthonormalisation).  `cold` starts from M * Omega (Omega a
 // fixed generic block), except in the groups whose lanes set `keep`, which
-// start from v; otherwise v is the warm start of every group.  A group has converged
+// take M * v instead (v a neighbouring pixel's basis, which does not pass
+// the test on its own); otherwise v is the warm start of every group.  A group has converged
 // when ||M V - V (V^H M V)||_F <= tol ||M V||_F for the basis entering a step;
 // that step's orthonormalised M V is kept and the group's basis is frozen.
 // The loop runs until every group has converged or max_steps; each group's
@@ -291,9 +292,8 @@ __device__ __forceinline__ int group_subspace(const float2 (&mrow)[D], bool row_
     for (int c = 0; c < RM; ++c)
       if (!keep) v[c] = (row_ok && c < r) ? cto<C>(omega(kk, c)) : czero<C>();
   }
-  // a warm start is tested on the first step (a cold group tested there
-  // does not pass: M Omega leaves the span of Omega)
-  bool tested = !cold || __ballot(keep) != 0;
+  // a start block (Omega, or a kept v) is not tested on the first step
+  bool tested = !cold;
   bool done = false;
   int step = 0;
   while (true) {
