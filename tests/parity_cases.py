@@ -142,11 +142,11 @@ HDR_SCATTERERS = ((0.55, 0.45, 0.0), (0.3, 0.7, 10.0), (0.75, 0.25, 20.0))
 # these (frame pass with the sliding window, and the probe's full sums, which
 # err alike, so the sliding window is not what limits them):
 #   plain FP32 path (FP32 covariance and solves): max error 1.4e-5 at 40 dB,
-#     1.5e-4 - 3.2e-4 at 50 dB, 2e-3 - 2e-1 at 60 dB;
+#     1.5e-4 - 3.2e-4 at 50 dB, 1.5e-3 - 6.2e-1 at 60 dB;
 #   mixed path (split-BF16 covariance, FP64 solves): 2.7e-6 at 40 dB,
 #     3.7e-5 - 5.9e-3 at 50 dB (scene-dependent, and on one scene moved
 #     from 5.9e-3 to 7.9e-5 by last-place changes in the FP32 sweep scale
-#     factors), 3.8e-3 at 60 dB.  Its products resolve about 2^-17 of each
+#     factors), 3.8e-3 - 1.9e-2 at 60 dB.  Its products resolve about 2^-17 of each
 #     product; an FP64 emulation of exactly that split puts the 60 dB error
 #     at 1.8e-3 from the covariance alone.
 # Both paths hold the 1e-4 bar up to 40 dB over the noise (10 dB over the
@@ -156,11 +156,11 @@ HDR_ENVELOPE_TOL = {
     "bf16x3_p3q16_50db": 1e-2,
 }
 HDR_OUTSIDE_ENVELOPE = {
-    "fp32_p3q16_60db": "FP32 covariance and eigensolves resolve 60 dB scatterers to about 1e-1 (FP32 envelope: 40 dB)",
+    "fp32_p3q16_60db": "FP32 covariance and eigensolves resolve 60 dB scatterers to about 1e-1 - 6e-1 (FP32 envelope: 40 dB)",
     "fp32_p3q8_60db": "FP32 covariance and eigensolves resolve 60 dB scatterers to about 2e-3 (FP32 envelope: 40 dB)",
     "fp32_p5q24_60db": "FP32 covariance and eigensolves resolve 60 dB scatterers to about 1e-1 (FP32 envelope: 40 dB)",
-    "bf16x3_p3q16_60db": "split-BF16 products resolve ~2^-17 of a product: a 60 dB scatterer gives ~4e-3 (mixed "
-                         "envelope: 40 dB)",
+    "bf16x3_p3q16_60db": "split-BF16 products resolve ~2^-17 of a product: a 60 dB scatterer gives 4e-3 - 2e-2 "
+                         "(mixed envelope: 40 dB)",
 }
 
 
