@@ -154,8 +154,7 @@ stap_status stap_valid_region(const stap_plan_t* plan, int32_t H, int32_t W,
  * (r, c), or (-1, -1) for a position past the frame's edge, and move[i] = the
  * one-pixel move (0 right, 1 left, 2 down) from the previous position whose
  * covariance this position's may update, or -1 where a sliding-window chain
- * starts (every 64 positions: four units down a column of units).  move may
- * be NULL.
+ * starts (every 16 positions, every 64 for p*q > 64).  move may be NULL.
  * Errors: INVALID_ARG (NULL, negative sizes, range outside the order). */
 stap_status stap_plan_order(const stap_plan_t* plan, int32_t H, int32_t W, int64_t first, int64_t count,
                             int32_t* pix, int32_t* move);
@@ -347,14 +346,13 @@ stap_status stap_sinr_loss(const stap_true_cov* cov, const stap_filter_set* filt
  *
  * stap_batch_create validates every tile, uploads a tile table to device
  * memory it owns, numbers the work items (runs of `pix_per_item` consecutive
- * positions of one tile's tiled pixel order, rounded up to a multiple of the
- * 64-position sliding-window chain)
+ * positions of one tile's tiled pixel order, rounded up to a multiple of 16)
  * longest tile first within each kernel class, and
  * builds one HIP graph: a counter-reset kernel node followed, as parallel
  * branches, by one persistent kernel node per kernel class present; every
  * workgroup of a persistent kernel pops work items from a device counter until
  * the queue is empty.  pix_per_item = 0 takes, per kernel class, the tuned
- * entry of the tuning cache for the current device (else 64 positions and a
+ * entry of the tuning cache for the current device (else 16 positions and a
  * grid of compute units x 8); pix_per_item > 0 applies to every class.  Results are bitwise equal to
  * stap_run on each tile alone.  The frames and outputs named by the tiles must
  * stay valid while the batch is launched.  Must be called with the device that
@@ -378,7 +376,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
 stap_status stap_batch_launch(stap_batch_t* batch, void* hip_stream);
 
 /* Autotuner: for every kernel class of the batch, alone, times (synchronously,
- * on hip_stream, with direct launches) work items of {64, 128, 256, 512}
+ * on hip_stream, with direct launches) work items of {16, 32, 64, 128}
  * positions and persistent grids of {1, 2, 4} x (compute units x 8)
  * workgroups, keeps each class's fastest, rebuilds the graph, and records the
  * choices in the tuning cache (stap_tune_record) keyed by (device
@@ -404,8 +402,8 @@ stap_status stap_batch_class_info(const stap_batch_t* batch, int32_t cls, int32_
  * class's entry for the current device.  arch = NULL means the current
  * device's architecture (e.g. "gfx950").
  * stap_tune_lookup: *found = 1 and the entry, or *found = 0 and the defaults
- *   (64, 1).  Errors: INVALID_ARG (found is NULL).
- * stap_tune_record: pix_per_item a multiple of 64 in [64, 4096], grid_mult
+ *   (16, 1).  Errors: INVALID_ARG (found is NULL).
+ * stap_tune_record: pix_per_item a multiple of 16 in [16, 4096], grid_mult
  *   in [1, 64]; ms is informative.  Errors: INVALID_ARG (also: the file
  *   cannot be written). */
 stap_status stap_tune_lookup(const char* arch, int32_t p, int32_t q, int32_t r_b, int32_t precision,

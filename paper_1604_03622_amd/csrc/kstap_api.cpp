@@ -28,7 +28,7 @@ namespace {
 struct BatchClass {
   int cls = -1;                  // kernel class
   std::vector<int32_t> order;    // tiles of this class, longest first
-  int ppb = kstap::kChainNarrow;  // work-item size (tiled-order positions, a multiple of the chain)
+  int ppb = 16;                  // work-item size (tiled-order positions, a multiple of the chain)
   int grid_mult = 1;             // persistent grid = compute units x 8 x grid_mult
 };
 
@@ -839,7 +839,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
     }
   }
   // work-item size and grid per class: as given, else the tuned entry of the
-  // class for this device, else one chain and CUs x 8 workgroups
+  // class for this device, else 16 positions and CUs x 8 workgroups
   const std::string arch = kstap::tune::device_arch();
   for (BatchClass& c : b->classes) {
     std::stable_sort(c.order.begin(), c.order.end(), [&](int32_t a, int32_t z) { return cost[a] > cost[z]; });
@@ -848,8 +848,7 @@ stap_status stap_batch_create(const stap_tile* tiles, int32_t ntiles, int32_t pi
     } else {
       int cp, cq, crb, cprec;
       kstap::tune::Entry e;
-      if (kstap::class_shape(c.cls, &cp, &cq, &crb, &cprec) && kstap::tune::lookup(arch, cp, cq, crb, cprec, &e) &&
-          e.ppb % kstap::kChainNarrow == 0) {
+      if (kstap::class_shape(c.cls, &cp, &cq, &crb, &cprec) && kstap::tune::lookup(arch, cp, cq, crb, cprec, &e)) {
         c.ppb = e.ppb;
         c.grid_mult = e.grid_mult;
       }
@@ -912,9 +911,9 @@ stap_status stap_batch_tune(stap_batch_t* batch, void* hip_stream, int32_t* best
     (void)hipEventDestroy(e0);
     return fail(STAP_ERR_DEVICE, "event create failed");
   }
-  // per class: work items of 1, 2, 4, 8 chains x persistent grids of 1, 2,
-  // 4 x (CUs x 8) workgroups, the class alone
-  const int ppbs[] = {kstap::kChainNarrow, 2 * kstap::kChainNarrow, 4 * kstap::kChainNarrow, 8 * kstap::kChainNarrow};
+  // per class: work items of 16..128 positions (multiples of the chain) x
+  // persistent grids of 1, 2, 4 x (CUs x 8) workgroups, the class alone
+  const int ppbs[] = {16, 32, 64, 128};
   const int mults[] = {1, 2, 4};
   stap_status st = batch_launch_direct(batch, s, true, int(batch->classes.size()));   // the splits only
   double total = 0.0;
@@ -1002,7 +1001,7 @@ stap_status stap_tune_lookup(const char* arch, int32_t p, int32_t q, int32_t r_b
   const std::string a = arch ? std::string(arch) : kstap::tune::device_arch();
   kstap::tune::Entry e;
   *found = kstap::tune::lookup(a, p, q, r_b <= 4 ? 4 : 8, precision, &e) ? 1 : 0;
-  if (pix_per_item) *pix_per_item = *found ? e.ppb : kstap::kChainNarrow;
+  if (pix_per_item) *pix_per_item = *found ? e.ppb : 16;
   if (grid_mult) *grid_mult = *found ? e.grid_mult : 1;
   return ok();
 }

@@ -165,15 +165,16 @@ __host__ __device__ inline bool tiled_pixel(int64_t pos, int H, int W, int* r, i
 
 // Sliding-window chains: every position but a chain's first is a one-pixel
 // move from the position before it, so its covariance can be updated from
-// that pixel's.  A chain spans four units down one column of units (64
-// positions) for both kernel families: a chain's first pixel sums all n
-// vectors, every other one adds and removes the few that enter and leave its
-// stencil, so longer chains take fewer full sums (at p = 3, q = 16, n = 200:
-// 194 MFMAs per pixel against 234 with one-unit chains), and a 2048 x 2048
-// frame still holds 65 536 of them.  Runs of positions given to a workgroup
-// start on a chain, so the chains, and the results, are the same for every
-// decomposition of a frame.
-constexpr int kChainNarrow = 4 * kUnit * kUnit;
+// that pixel's.  A chain spans one unit for the narrow kernels (16 positions:
+// short runs keep many workgroups in flight) and four units down one column
+// of units for the wide kernels (64: a wide pixel's full sum costs more).
+// Narrow runs of 64 positions take a quarter of the full sums, but the ~256
+// workgroups in flight on one XCD then cover four times the pixels, whose
+// training windows no longer fit in that XCD's L2: on a 2048 x 2048 p=3 q=16
+// frame its misses grew from 2.0 to 28 GB per launch for a 1.5 % shorter run.
+// Runs of positions given to a workgroup start on a chain, so the chains, and
+// the results, are the same for every decomposition of a frame.
+constexpr int kChainNarrow = kUnit * kUnit;
 constexpr int kChainWide = 4 * kUnit * kUnit;
 
 // The move that reaches position pos from pos - 1, or -1 if pos starts a chain

@@ -12,7 +12,7 @@ namespace kstap {
 namespace tune {
 
 struct Entry {
-  int ppb = 64;         // work-item size in tiled-order positions (a multiple of the sliding-window chain)
+  int ppb = 16;         // work-item size in tiled-order positions (a multiple of the sliding-window chain)
   int grid_mult = 1;    // persistent grid = compute units x 8 x grid_mult workgroups
   double ms = 0.0;      // time of the class alone when it was tuned
 };

@@ -115,7 +115,7 @@ def test_order_visits_every_pixel_once_and_moves_are_neighbours(p, q, H, W):
     seen = pix[inside]
     assert len(seen) == H * W
     assert len({(int(r), int(c)) for r, c in seen}) == H * W
-    chain = 64   # four units down a column of units, for every kernel family
+    chain = 64 if p * q > 64 else 16
     assert np.all(mv[::chain] == -1)
     for i in np.nonzero(mv >= 0)[0]:
         if not (inside[i] and inside[i - 1]):
@@ -123,7 +123,7 @@ def test_order_visits_every_pixel_once_and_moves_are_neighbours(p, q, H, W):
         dr, dc = MOVE_D[int(mv[i])]
         assert tuple(pix[i] - pix[i - 1]) == (dr, dc), (i, pix[i - 1], pix[i], mv[i])
     # chains are long: only a few positions start one
-    assert np.mean(mv == -1) <= 2.5 / chain
+    assert np.mean(mv == -1) <= (1.5 / chain if chain == 16 else 2.5 / chain)
 
 
 @pytest.mark.parametrize("n", [64, 128, 200, 256])
