@@ -804,6 +804,21 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
   // off-diagonal / diagonal tiles (four-product form); p2, p3: P2 and P3
   f4 accR[NT], accI[(K3 || NO == 0) ? 1 : NO], accD[K3 ? 1 : NB];
   f4 p2[K3 ? NT : 1], p3[K3 ? NT : 1];
+  // one chunk stream: the entering vectors' chunks, then the leaving ones';
+  // chunk c + 1 is fetched while chunk c is accumulated.  Fetching one chunk
+  // past the end reads the leaving list's kOut entries (KD > kMaxDelta + 6),
+  // i.e. zeros, and is never used.
+  const int na = (nadd + 3) >> 2, nch = na + ((nrem + 3) >> 2);
+  __amdgpu_buffer_rsrc_t rs[NB];
+#pragma unroll
+  for (int I = 0; I < NB; ++I) rs[I] = block_rsrc<Q>(xwin, plane, rec, I);
+  auto fetch = [&](int c, float2 (&v)[NB]) __attribute__((always_inline)) {
+    const uint32_t off = (c < na ? sAdd + 4 * c : sRem + 4 * (c - na))[lane >> 4];
+#pragma unroll
+    for (int I = 0; I < NB; ++I) v[I] = bload(rs[I], loff[I] + off);
+  };
+  float2 vc[NB], vn[NB];
+  fetch(0, vc);   // in flight while the old S is reloaded
   {
     int t = 0, u = 0;
 #pragma unroll
@@ -828,20 +843,16 @@ __device__ __forceinline__ void scm_fp32_delta(const float2* xwin, int64_t plane
         ++t;
       }
   }
-  __amdgpu_buffer_rsrc_t rs[NB];
-#pragma unroll
-  for (int I = 0; I < NB; ++I) rs[I] = block_rsrc<Q>(xwin, plane, rec, I);
 #pragma unroll 1
-  for (int pass = 0; pass < 2; ++pass) {
-    const uint32_t* tab = pass ? sRem : sAdd;
-    const int cnt = pass ? nrem : nadd;
-    const float sg = pass ? -1.f : 1.f;
-#pragma unroll 1
-    for (int ch = 0; ch < (cnt + 3) >> 2; ++ch) {
-      const uint32_t off = tab[ch * 4 + (lane >> 4)];
+  for (int ch = 0; ch < nch; ++ch) {
+    {
+      fetch(ch + 1, vn);
+      const float sg = ch < na ? 1.f : -1.f;
       float2 v[NB];
 #pragma unroll
-      for (int I = 0; I < NB; ++I) v[I] = bload(rs[I], loff[I] + off);
+      for (int I = 0; I < NB; ++I) v[I] = vc[I];
+#pragma unroll
+      for (int I = 0; I < NB; ++I) vc[I] = vn[I];
       if constexpr (K3) {
         float xr[NB], xi[NB], a1[NB], a2[NB], a3[NB], b3[NB];
 #pragma unroll
