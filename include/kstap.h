@@ -141,7 +141,8 @@ stap_status stap_plan_info(const stap_plan_t* plan, double* tau, int32_t* window
  * (2*n int32).  Errors: INVALID_ARG. */
 stap_status stap_plan_stencil(const stap_plan_t* plan, int32_t* out);
 
-/* Half-open valid region [r0, r1) x [c0, c1) of an H x W frame; empty
+/* Half-open valid region [r0, r1) x [c0, c1) of an H x W frame: the pixels
+ * whose whole training stencil (the range bins of Sec. 1.1) lies in the frame; empty
  * (r0 == r1 or c0 == c1) if the stencil does not fit.  Errors: INVALID_ARG. */
 stap_status stap_valid_region(const stap_plan_t* plan, int32_t H, int32_t W,
                               int32_t* r0, int32_t* r1, int32_t* c0, int32_t* c1);
@@ -168,7 +169,12 @@ stap_status stap_plan_order(const stap_plan_t* plan, int32_t H, int32_t W, int64
 stap_status stap_plan_moves(const stap_plan_t* plan, int32_t move, int32_t* nadd, int32_t* nrem, int32_t* add,
                             int32_t* rem);
 
-/* Whole-frame pass.  x: device complex64 [p][H][W][q]; T: device float [H][W];
+/* Whole-frame pass: for every valid pixel, the sample covariance of Eq. (2)
+ * (Sec. 1.1) over the plan's training stencil, LR-Kron (Sec. 4, Algorithm 2,
+ * on the rearrangement of Algorithm 1, started from Eqs. (18)-(19)), the
+ * rank-r_a / rank-r_b subspaces of the factors, the statistic of Eq. (25)
+ * (Sec. 5; Eq. (26) of Sec. 6.3 for the GLRT over h), and D = T > tau.
+ * x: device complex64 [p][H][W][q]; T: device float [H][W];
  * D: device uint8 [H][W] or NULL.  Every element of T (and D) is written.
  * 1 <= H, W and p*H*W*q < 2^31.  Enqueued on hip_stream (hipStream_t).
  * Errors: INVALID_ARG, UNSUPPORTED, DEVICE (launch failed). */
@@ -240,7 +246,8 @@ stap_status stap_run_noalloc(const stap_plan_t* plan, const void* x, int32_t H, 
                              float* T, uint8_t* D, void* hip_stream);
 
 /* Per-pixel probe: the same computation for a list of pixels, with the
- * intermediate results.  All pointers are device memory:
+ * intermediate results (the subspaces of the LR-Kron factors of Sec. 4,
+ * Algorithm 2, its residual eta and iteration count, and Eq. (25)'s T).  All pointers are device memory:
  *   pix   int32 [npix][2] (r, c)   (pixels outside the valid region get T = 0,
  *                                   eta = 0, iters = 0, zero bases)
  *   UA    complex64 [npix][p][r_a]  orthonormal basis of the space subspace
@@ -342,7 +349,9 @@ stap_status stap_sinr_loss(const stap_true_cov* cov, const stap_filter_set* filt
                            int32_t na, const float* b_grid, int32_t nb, float* loss, void* hip_stream);
 
 /* Batched uneven tiles (tiles may differ in p, q, n, ranks, steering,
- * precision and size; each has its own plan, frame and outputs).
+ * precision and size; each has its own plan, frame and outputs).  Every tile
+ * gets stap_run's per-pixel computation: Eq. (2) of Sec. 1.1, Algorithm 2 of
+ * Sec. 4 and Eq. (25) of Sec. 5.
  *
  * stap_batch_create validates every tile, uploads a tile table to device
  * memory it owns, numbers the work items (runs of `pix_per_item` consecutive
@@ -425,7 +434,9 @@ stap_status stap_batch_destroy(stap_batch_t* batch);
  * destroy. */
 stap_status stap_run_batch(const stap_tile* tiles, int32_t ntiles, void* hip_stream);
 
-/* Serving with continuous batching.
+/* Serving with continuous batching: frames arriving over time get
+ * stap_run's per-pixel computation (Eq. (2) of Sec. 1.1, Algorithm 2 of
+ * Sec. 4, Eq. (25) of Sec. 5).
  *
  * A server owns an HBM arena of hbm_budget_bytes (allocated on the current
  * device at creation), a copy stream, a compute stream and a worker thread.
