@@ -77,7 +77,7 @@ def executed_vectors(plan, H, W, slides):
     predecessor in the order is a valid pixel updates that pixel's n S with
     the vectors entering and leaving the stencil; every other valid pixel sums
     all n.  `slides` is False for kernels that always take the full sum (the
-    narrow split-BF16 kernels).  Returns (vectors, valid pixels)."""
+    narrow kernels with FP64 solves).  Returns (vectors, valid pixels)."""
     pix, mv = plan.order(H, W)
     r0, r1, c0, c1 = plan.valid_region(H, W)
     valid = (pix[:, 0] >= r0) & (pix[:, 0] < r1) & (pix[:, 1] >= c0) & (pix[:, 1] < c1)
@@ -200,20 +200,22 @@ def _roofs(plan, H, W, sec, prec):
     return out
 
 
-def form_frame_mixed(kstap, torch, scene, steps):
-    """The same full frame with split-BF16 covariance and FP64 eigensolves."""
+def form_frame_mixed(kstap, torch, scene, steps, prec="bf16x3"):
+    """The same full frame with split-BF16 covariance and FP64 eigensolves
+    (bf16x3), or FP32 covariance full sums and FP64 eigensolves (fp32_f64)."""
     x = torch.from_numpy(scene.x).cuda()
-    plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4, precision="bf16x3")
+    plan = kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4, precision=prec)
     H, W = x.shape[1], x.shape[2]
     T = torch.empty(x.shape[1:3], device="cuda")
     D = torch.empty(x.shape[1:3], dtype=torch.uint8, device="cuda")
     r0, r1, c0, c1 = plan.valid_region(H, W)
     sec = _timed(torch, lambda: kstap.run(plan, x, T, D), steps)
     px = (r1 - r0) * (c1 - c0)
-    out = dict(workload="full frame 2048x2048 p=3 q=16 n=200, bf16x3 covariance + FP64 eigensolves",
+    cov = "bf16x3 covariance" if prec == "bf16x3" else "FP32 covariance (full sums)"
+    out = dict(workload=f"full frame 2048x2048 p=3 q=16 n=200, {cov} + FP64 eigensolves",
                pixels_per_s=px / sec, ms=sec * 1e3,
-               bound="valu (FP64 solves and BF16 operand gathers; see the kernel profile)")
-    out.update(_roofs(plan, H, W, sec, "bf16x3"))
+               bound="valu (FP64 solves; see the kernel profile)")
+    out.update(_roofs(plan, H, W, sec, prec))
     return out
 
 
@@ -504,6 +506,8 @@ def system_forms(kstap, torch, args, scene):
     forms = {}
     forms["frame_bf16x3"] = form_frame_mixed(kstap, torch, scene, max(3, args.steps // 2))
     _log(f"frame bf16x3: {forms['frame_bf16x3']['pixels_per_s'] / 1e6:.1f} Mpx/s")
+    forms["frame_fp32_f64"] = form_frame_mixed(kstap, torch, scene, max(3, args.steps // 2), "fp32_f64")
+    _log(f"frame fp32_f64: {forms['frame_fp32_f64']['pixels_per_s'] / 1e6:.1f} Mpx/s")
     torch.cuda.empty_cache()
     forms["mixed_workload"] = form_wide_mixed(kstap, torch, 3)
     torch.cuda.empty_cache()

@@ -56,8 +56,12 @@ typedef enum {
 
 typedef enum {
   STAP_PREC_FP32 = 0,   /* covariance on FP32 MFMA, everything else FP32 (eta terms FP64) */
-  STAP_PREC_BF16X3 = 1  /* covariance as three BF16 MFMA products (hi*hi + hi*lo + lo*hi) with
+  STAP_PREC_BF16X3 = 1, /* covariance as three BF16 MFMA products (hi*hi + hi*lo + lo*hi) with
                            FP32 accumulation; eigensolves and normalisation in FP64 */
+  STAP_PREC_FP32_FP64 = 2 /* covariance on FP32 MFMA as full sums (no sliding-window update),
+                             eigensolves and normalisation in FP64: for frames with point
+                             scatterers far above the clutter; built for p = 3, q in {8, 16},
+                             r_b <= 4 (other shapes: UNSUPPORTED) */
 } stap_precision;
 
 typedef enum {

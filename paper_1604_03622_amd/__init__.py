@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libkstap.so")
 STAP_OK = 0
 STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE", 5: "BUSY",
                 6: "INTERNAL"}
-PRECISIONS = {"fp32": 0, "bf16x3": 1}
+PRECISIONS = {"fp32": 0, "bf16x3": 1, "fp32_f64": 2}
 STAT_MODES = {"glrt": 0, "fixed": 1}
 FILTERS = {"kron": 0, "classical": 1}
 

@@ -17,7 +17,8 @@ BUILD = os.path.join(PKG, "_build")
 ARCH = os.environ.get("KSTAP_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kstap_kern_fp32.hip", "kstap_kern_bf16.hip", "kstap_kern_wide.hip", "kstap_dispatch.hip",
+SOURCES = ["kstap_kern_fp32.hip", "kstap_kern_bf16.hip", "kstap_kern_wide.hip", "kstap_kern_f32f64.hip",
+           "kstap_dispatch.hip",
            "kstap_largeq.hip", "kstap_lrstap.hip",
            "kstap_api.cpp", "kstap_host.cpp", "kstap_server.cpp", "kstap_tune.cpp"]
 FLAGS = [

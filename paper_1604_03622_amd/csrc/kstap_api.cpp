@@ -328,7 +328,7 @@ stap_status stap_plan_create(const stap_config* cfg, stap_plan_t** out) {
     return fail(STAP_ERR_INVALID_ARG, "unknown stat_mode %d", c.stat_mode);
   if (c.stat_mode == STAP_STAT_FIXED && !c.h_steer)
     return fail(STAP_ERR_INVALID_ARG, "STAP_STAT_FIXED needs h_steer");
-  if (c.precision != STAP_PREC_FP32 && c.precision != STAP_PREC_BF16X3)
+  if (c.precision != STAP_PREC_FP32 && c.precision != STAP_PREC_BF16X3 && c.precision != STAP_PREC_FP32_FP64)
     return fail(STAP_ERR_INVALID_ARG, "unknown precision %d", c.precision);
   if (!(c.tau > 0.0) && !(c.pfa > 0.0 && c.pfa < 1.0))
     return fail(STAP_ERR_INVALID_ARG, "need tau > 0 or 0 < pfa < 1");

@@ -1336,10 +1336,12 @@ __device__ __forceinline__ void tail_batch(const KParams& prm, const float2 (&Bq
 
 // PREC 0: FP32 covariance, FP32 eigensolves and statistic.
 // PREC 1: split-BF16 covariance, FP64 eigensolves and statistic.
+// PREC 2: FP32 covariance (full sums, no sliding window), FP64 eigensolves
+//         and statistic.
 // LDS carve-out of one pixel pipeline (one workgroup), largest alignment first.
 template <int P, int Q, int RBM, int PREC>
 struct Lds {
-  using EC = typename Pick<PREC == 1, double2, float2>::type;
+  using EC = typename Pick<PREC != 0, double2, float2>::type;
   static constexpr int PQ = P * Q;
   static constexpr int RAM = (P < kMaxRA) ? P : kMaxRA;
   static constexpr int G = Groups<Q>::G;
@@ -1348,7 +1350,7 @@ struct Lds {
   // tail's basis exchange, and the FP32 path's diagonal-tile transpose
   static constexpr size_t kB = sizeof(float2) * Q * Q;
   static constexpr size_t kT = sizeof(EC) * RBM * Q * G;
-  static constexpr size_t kP = PREC ? 0 : sizeof(float) * NB * 256;
+  static constexpr size_t kP = PREC == 1 ? 0 : sizeof(float) * NB * 256;
   static constexpr size_t kBT = kB > kT ? (kB > kP ? kB : kP) : (kT > kP ? kT : kP);
   static constexpr size_t oUA = 0;                                        // EC[P*RAM]
   static constexpr size_t oAh = oUA + sizeof(EC) * P * RAM;               // EC[P*P]
@@ -1370,7 +1372,7 @@ struct Lds {
 // mode).  One 64-lane workgroup; `lds` holds Lds<...>::bytes.
 template <int P, int Q, int RBM, int MODE, int PREC, bool VAR = false>
 __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, int64_t count, char* lds) {
-  using EC = typename Pick<PREC == 1, double2, float2>::type;   // eigensolver / statistic precision
+  using EC = typename Pick<PREC != 0, double2, float2>::type;   // eigensolver / statistic precision
   using ES = decltype(EC{}.x);
   using L = Lds<P, Q, RBM, PREC>;
   constexpr int PQ = P * Q;
@@ -1404,7 +1406,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 
   // byte offset of each stencil entry from the window origin (kOut past n);
   // samples are complex64 (8 bytes) or, on the mixed path, BF16 pairs (4)
-  constexpr int kSample = PREC ? 4 : 8;
+  constexpr int kSample = PREC == 1 ? 4 : 8;
   wave_sync();
   for (int m = lane; m < kMaxN + kOffPad; m += 64)
     sOffB[m] = (m < n) ? uint32_t(((int(prm.st[2 * m]) * W + int(prm.st[2 * m + 1])) * Q - prm.st_min) * kSample)
@@ -1515,8 +1517,8 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
     const int64_t win = (int64_t(r) * W + c) * Q + prm.st_min;
 
     // ---------------------------------------------------------------- a2 SCM
-    // (the mixed path is bound by its FP64 solves, not by the cheaper BF16
-    // MFMAs, so it always takes the full sum)
+    // (the FP64-solve paths are bound by their solves, not by the covariance
+    // MFMAs, so they always take the full sum: no sliding-window residue)
     const int mv = tiled_move(first + it, H, W, kChainNarrow);
     const bool slide = PREC == 0 && MODE == kModeRun && left_ok && mv >= 0 && prm.nadd[0] >= 0;
     // q a multiple of 16: the block sums and ||S||^2 of a4 are gathered while
@@ -1526,7 +1528,7 @@ __device__ __forceinline__ void run_pixels(const KParams& prm, int64_t first, in
 #pragma unroll
     for (int e = 0; e < P * P; ++e) ss.a0[e] = cz();
     ss.nr = 0.f;
-    if constexpr (PREC == 0) {
+    if constexpr (PREC != 1) {
       if (slide)
         scm_fp32_delta<P, Q>(prm.x + win, plane, prm.rec_bytes, sDelta + 2 * mv * KD, prm.nadd[mv],
                              sDelta + (2 * mv + 1) * KD, prm.nrem[mv], loff, n, sS, ss);

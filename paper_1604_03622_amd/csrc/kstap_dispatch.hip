@@ -12,6 +12,7 @@ namespace kstap {
 const Entry* entries_fp32(int* count);
 const Entry* entries_bf16(int* count);
 const Entry* entries_wide(int* count);
+const Entry* entries_f32f64(int* count);
 
 namespace {
 
@@ -36,7 +37,7 @@ __global__ void reset_counters(unsigned long long* c, int n) {
 const std::vector<const Entry*>& table() {
   static const std::vector<const Entry*> t = [] {
     std::vector<const Entry*> v;
-    for (auto part : {&entries_fp32, &entries_bf16, &entries_wide}) {
+    for (auto part : {&entries_fp32, &entries_bf16, &entries_wide, &entries_f32f64}) {
       int n = 0;
       const Entry* e = part(&n);
       for (int i = 0; i < n; ++i) v.push_back(&e[i]);

@@ -109,6 +109,8 @@ CLASSES = {
     "fp32_p6q8_ra2": (6, 8, 128, 2, 3, "fp32", 64),
     "bf16x3_p3q12_rb3": (3, 12, 128, 1, 3, "bf16x3", 72),
     "bf16x3_p3q16_rb6_ra2": (3, 16, 256, 2, 6, "bf16x3", 80),
+    "fp32_f64_p3q8": (3, 8, 64, 1, 3, "fp32_f64", 64),
+    "fp32_f64_p3q16_ra2": (3, 16, 200, 2, 4, "fp32_f64", 72),
 }
 
 
@@ -135,6 +137,16 @@ HDR = {
     "fp32_p3q8_60db": (3, 8, 64, 3, "fp32", 56, 60.0),
     "fp32_p5q24_60db": (5, 24, 256, 4, "fp32", 44, 60.0),
     "bf16x3_p3q16_60db": (3, 16, 200, 4, "bf16x3", 72, 60.0),
+    # FP32 covariance (full sums) with FP64 solves, on the FP32 cases' scenes
+    "fp32_f64_p3q16_50db": (3, 16, 200, 4, "fp32_f64", 72, 50.0),
+    "fp32_f64_p3q16_60db": (3, 16, 200, 4, "fp32_f64", 72, 60.0),
+    "fp32_f64_p3q8_60db": (3, 8, 64, 3, "fp32_f64", 56, 60.0),
+}
+# cases that reuse another precision's scene (same seed and scatterers)
+HDR_SAME_SCENE = {
+    "fp32_f64_p3q16_50db": "fp32_p3q16_60db",
+    "fp32_f64_p3q16_60db": "fp32_p3q16_60db",
+    "fp32_f64_p3q8_60db": "fp32_p3q8_60db",
 }
 # (row, col) as fractions of the frame, dB below the case's strongest scatterer
 HDR_SCATTERERS = ((0.55, 0.45, 0.0), (0.3, 0.7, 10.0), (0.75, 0.25, 20.0))
@@ -161,13 +173,15 @@ HDR_OUTSIDE_ENVELOPE = {
     "fp32_p5q24_60db": "FP32 covariance and eigensolves resolve 60 dB scatterers to about 1e-1 (FP32 envelope: 40 dB)",
     "bf16x3_p3q16_60db": "split-BF16 products resolve ~2^-17 of a product: a 60 dB scatterer gives 4e-3 - 2e-2 "
                          "(mixed envelope: 40 dB)",
+    "fp32_f64_p3q16_60db": "FP32 accumulation of sums dominated by a 60 dB scatterer: p99 error 1.9e-5, worst "
+                           "pixel 7.2e-2 (FP32-covariance / FP64-solve envelope: 50 dB)",
 }
 
 
 def hdr_case(name):
     p, q, n, rb, prec, side, top = HDR[name]
     spec = scenegen.SceneSpec(p=p, q=q, H=side, W=side, r_a=1, r_b=rb, n_targets=3, snr_db=(5.0, 15.0))
-    stem = name.rsplit("_", 1)[0]   # the same scene at every scatterer strength
+    stem = HDR_SAME_SCENE.get(name, name).rsplit("_", 1)[0]   # the same scene at every scatterer strength
     return spec, scenegen.BASE_SEED + 400 + len(stem), dict(p=p, q=q, n=n, r_a=1, r_b=rb), prec
 
 

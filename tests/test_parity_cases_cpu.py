@@ -64,7 +64,7 @@ def test_strong_scatterer_case_grades_most_valid_pixels(name):
 def built_classes():
     """(p, q, r_b bound, precision) of every kernel in the instantiation tables."""
     out = set()
-    for f in ("kstap_kern_fp32.hip", "kstap_kern_bf16.hip", "kstap_kern_wide.hip"):
+    for f in ("kstap_kern_fp32.hip", "kstap_kern_bf16.hip", "kstap_kern_wide.hip", "kstap_kern_f32f64.hip"):
         txt = open(os.path.join(CSRC, f)).read()
         for m in re.finditer(r"KSTAP_ENTRY\((\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", txt):
             if "#define" in txt[max(0, m.start() - 8):m.start()]:
@@ -76,7 +76,7 @@ def built_classes():
 
 
 def reached_classes():
-    prec = {"fp32": 0, "bf16x3": 1}
+    prec = {"fp32": 0, "bf16x3": 1, "fp32_f64": 2}
     out = set()
     for spec, seed, base, pr in CASES.values():
         out.add((base["p"], base["q"], 4 if base["r_b"] <= 4 else 8, prec[pr]))
