@@ -536,7 +536,7 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=300)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
-    ap.add_argument("--only-form", choices=("large_q", "variants", "robustness"),
+    ap.add_argument("--only-form", choices=("large_q", "variants", "robustness", "frame_precisions"),
                     help="run one secondary form alone and print its JSON (for kernel profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -553,6 +553,10 @@ def main():
             out = form_large_q(kstap, torch, cpu=False)
         elif args.only_form == "robustness":
             out = form_robustness(kstap, torch, cpu=False)
+        elif args.only_form == "frame_precisions":
+            scene = scenegen.make_scene(WORKLOADS["full_frame"]["spec"])
+            out = {prec: form_frame_mixed(kstap, torch, scene, max(3, args.steps // 2), prec)
+                   for prec in ("bf16x3", "fp32_f64")}
         else:
             out = form_variants(kstap, torch)
         if args.calibrate_copy:

@@ -161,8 +161,12 @@ HDR_SCATTERERS = ((0.55, 0.45, 0.0), (0.3, 0.7, 10.0), (0.75, 0.25, 20.0))
 #     factors), 3.8e-3 - 1.9e-2 at 60 dB.  Its products resolve about 2^-17 of each
 #     product; an FP64 emulation of exactly that split puts the 60 dB error
 #     at 1.8e-3 from the covariance alone.
+#   FP32 covariance (full sums) with FP64 solves: within 1e-4 at 50 dB and on
+#     the q = 8 scene at 60 dB; on the q = 16 scene at 60 dB the 99th
+#     percentile stays at 1.9e-5 and the worst pixel reaches 7.2e-2 (FP32
+#     accumulation of sums that the scatterer dominates).
 # Both paths hold the 1e-4 bar up to 40 dB over the noise (10 dB over the
-# clutter).  The mixed 50 dB case straddles it and is graded against its
+# clutter), the FP32 / FP64 form up to 50 dB.  The mixed 50 dB case straddles it and is graded against its
 # envelope's bound; the 60 dB cases are expected to fail the bar.
 HDR_ENVELOPE_TOL = {
     "bf16x3_p3q16_50db": 1e-2,
