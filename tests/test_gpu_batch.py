@@ -31,6 +31,43 @@ def _setup(seed=4):
     return kstap, tiles, refs
 
 
+def test_batch_fp32_f64_tiles_equal_alone_and_oracle():
+    """Tiles with FP32 covariance and FP64 solves beside a plain FP32 tile in
+    one batch: the persistent kernels of that precision give each tile's
+    solo result bitwise, and the oracle's within the 1e-4 bar."""
+    import paper_1604_03622_amd as kstap
+    tiles, refs = [], []
+    for i, (q, n, rb, prec, H, W) in enumerate([(8, 64, 3, "fp32_f64", 38, 43), (16, 200, 4, "fp32_f64", 46, 41),
+                                                (16, 200, 4, "fp32", 44, 44)]):
+        spec = scenegen.SceneSpec(p=3, q=q, H=H, W=W, r_a=1, r_b=rb, n_targets=2)
+        sc = scenegen.make_scene(spec, seed=1100 + i)
+        plan = kstap.Plan(p=3, q=q, n=n, r_a=1, r_b=rb, precision=prec)
+        x = torch.from_numpy(sc.x).cuda()
+        T = torch.full((H, W), -1.0, device="cuda")
+        D = torch.full((H, W), 7, dtype=torch.uint8, device="cuda")
+        tiles.append((plan, x, T, D))
+        refs.append((sc, dict(p=3, q=q, n=n, r_a=1, r_b=rb)))
+    print("fp32_f64 batch of", len(tiles), "tiles", flush=True)
+    b = kstap.Batch(tiles)
+    assert b.info()["classes"] == 3
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (plan, x, T, D) in enumerate(tiles):
+        Ta, Da = kstap.run(plan, x)
+        torch.cuda.synchronize()
+        assert torch.equal(T, Ta), f"tile {i}: batched T differs from the tile alone"
+        assert torch.equal(D, Da), f"tile {i}: batched D differs from the tile alone"
+        sc, cfg = refs[i]
+        ref = oracle.kron_stap_frame(sc.x, oracle.OracleConfig(**cfg))
+        Tg = T.cpu().numpy()
+        pix = ref["pixels"]
+        e = np.abs(Tg[pix[:, 0], pix[:, 1]] - ref["T"]) / np.maximum(ref["T"], 1.0)
+        g = (oracle.relative_gaps(ref["lam_B"], cfg["r_b"]) >= 1e-3) & (oracle.relative_gaps(ref["lam_A"], cfg["r_a"]) >= 1e-3)
+        print(f"tile {i} {cfg} {plan.precision}: graded {int(g.sum())}/{g.size} max err {e[g].max():.2e}", flush=True)
+        assert g.sum() >= 0.8 * g.size
+        assert e[g].max() <= 1e-4
+
+
 def test_batch_equals_tiles_alone_and_oracle():
     kstap, tiles, refs = _setup()
     print("batch of", len(tiles), "tiles", flush=True)

@@ -47,6 +47,29 @@ def test_server_results_equal_alone_and_small_frames_overtake():
     srv.close()
 
 
+def test_server_fp32_f64_frames_equal_alone():
+    """Frames with FP32 covariance and FP64 solves served beside a plain FP32
+    frame: the server's persistent steps give each frame's solo result."""
+    import paper_1604_03622_amd as kstap
+    plans = [kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4, precision="fp32_f64"),
+             kstap.Plan(p=3, q=8, n=64, r_a=1, r_b=3, precision="fp32_f64"),
+             kstap.Plan(p=3, q=16, n=200, r_a=1, r_b=4)]
+    data = []
+    for i, (pl, H, W) in enumerate(zip(plans, (120, 90, 100), (100, 77, 96))):
+        sc = scenegen.make_scene(scenegen.SceneSpec(p=3, q=pl.q, H=H, W=W, r_b=pl.r_b, n_targets=3), 340 + i)
+        data.append((pl, torch.from_numpy(sc.x).pin_memory()))
+    print("server: 3 frames, two fp32_f64", flush=True)
+    srv = kstap.Server(hbm_budget_bytes=1 << 30, max_inflight=4, step_pixels=1 << 13)
+    tickets = [srv.submit(pl, x) for pl, x in data]
+    results = [srv.wait(t, timeout_ms=120000) for t in tickets]
+    for (pl, x), (T, D, _) in zip(data, results):
+        Ta, Da = kstap.run(pl, x.cuda())
+        torch.cuda.synchronize()
+        assert torch.equal(T, Ta.cpu()), f"served T differs from the frame alone ({pl.precision})"
+        assert torch.equal(D, Da.cpu()), f"served D differs from the frame alone ({pl.precision})"
+    srv.close()
+
+
 def test_server_budget_admission():
     import paper_1604_03622_amd as kstap
     pl = kstap.Plan(p=3, q=8, n=64, r_a=1, r_b=3)

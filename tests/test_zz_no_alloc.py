@@ -31,7 +31,7 @@ def _both(kstap, plan, x):
     return T1.cpu().numpy(), D1.cpu().numpy(), T2.cpu().numpy(), D2.cpu().numpy()
 
 
-@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32", "fp32_f64"])
 def test_noalloc_equals_run_twice_shrinking(prec):
     kstap = _kstap()
     base = dict(p=3, q=16, n=200, r_a=1, r_b=4)
