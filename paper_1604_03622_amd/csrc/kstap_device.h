@@ -1140,8 +1140,12 @@ __device__ __forceinline__ void tail_batch(const KParams& prm, const float2 (&Bq
 #pragma unroll
   for (int c = 0; c < RBM; ++c)
     if (!keep) vb[c] = czero<EC>();
+  // FP64 solves iterate until converged where the r_b-th and next eigenvalues
+  // of B lie close together (a ratio of 0.99 takes ~1 500 steps to 1e-10);
+  // the loop exits on the step cap, so a group never runs unbounded
+  constexpr int kTailSteps = sizeof(ES) == 8 ? 4000 : 200;
   if (r_b > 0)
-    group_subspace<RBM, QP, Q, EC, WAVE_LOCAL>(Bq, rok && flag == 0, r_b, vb, scratch, true, 200, tol, keep);
+    group_subspace<RBM, QP, Q, EC, WAVE_LOCAL>(Bq, rok && flag == 0, r_b, vb, scratch, true, kTailSteps, tol, keep);
   vb_ok = rok && flag == 0;
   // statistic
   int pr, pc;
