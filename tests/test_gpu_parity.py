@@ -327,6 +327,49 @@ def test_kernel_class_parity(name):
     assert dA.max() <= 1e-4 and dB.max() <= 1e-4
 
 
+def regrade_stop_ties(kstap, plan, xd, Tg, ref, out, cfg, tol):
+    """Where several results are correct: LR-Kron stops at the first k with
+    |eta_k - eta_{k-1}| <= eps (Sec. 4, Algorithm 2), and where that test
+    lands within 0.1 % of eps the GPU (eta from its own covariance) may stop
+    one iteration earlier or later.  For such a graded pixel whose T misses
+    the bar and whose GPU iteration count (from the probe) differs from the
+    oracle's by one, the reference becomes the oracle run to the GPU's count.
+    Returns the reference T and the number of pixels re-graded."""
+    H, W = Tg.shape
+    T = ref["T"].copy()
+    g = graded_mask(ref, cfg.r_a, cfg.r_b)
+    bad = np.nonzero(g & (rel_err(Tg.ravel(), ref["T"]) > tol))[0]
+    if bad.size == 0 or bad.size > 64:
+        return T, 0
+    pix = np.stack([bad // W, bad % W], 1).astype(np.int32)
+    pr = kstap.probe(plan, xd, pix)
+    torch.cuda.synchronize()
+    kg = pr["iters"].cpu().numpy()
+    where = {(int(r), int(c)): i for i, (r, c) in enumerate(out["pixels"])}
+    st = cfg.training_stencil()
+    b_s = cfg.temporal_steering()
+    n = 0
+    for j, f in enumerate(bad):
+        r, c = int(pix[j, 0]), int(pix[j, 1])
+        ko = int(out["iters"][where[(r, c)]])
+        if abs(int(kg[j]) - ko) != 1:
+            continue
+        k = min(ko, int(kg[j]))
+        S = oracle.sample_covariance(xd.cpu().numpy(), np.array([r]), np.array([c]), st)
+        R = oracle.rearrange(S, cfg.p, cfg.q)
+        e1 = oracle.lr_kron(R, cfg.p, cfg.q, cfg.r_a, cfg.r_b, 0.0, k - 1, k - 1)["eta"][0]
+        e2 = oracle.lr_kron(R, cfg.p, cfg.q, cfg.r_a, cfg.r_b, 0.0, k, k)["eta"][0]
+        if abs(abs(e2 - e1) - cfg.eps) > 1e-3 * cfg.eps:
+            continue
+        est = oracle.lr_kron(R, cfg.p, cfg.q, cfg.r_a, cfg.r_b, 0.0, int(kg[j]), int(kg[j]))
+        Xt = oracle.snapshots(xd.cpu().numpy(), np.array([r]), np.array([c]))
+        T[f] = oracle.kron_stap_statistic(Xt, est["U_A"], est["U_B"], b_s)[0]
+        note(f"  stop-rule tie at ({r}, {c}): |d eta| {abs(e2 - e1):.4e} at k = {k}, oracle {ko} vs GPU "
+             f"{int(kg[j])} iterations; T {Tg[r, c]:.6g} against the oracle at {int(kg[j])}: {T[f]:.6g}")
+        n += 1
+    return T, n
+
+
 @pytest.mark.parametrize("name", [
     pytest.param(n, marks=pytest.mark.xfail(strict=True, reason=pc.HDR_OUTSIDE_ENVELOPE[n]))
     if n in pc.HDR_OUTSIDE_ENVELOPE else n for n in sorted(pc.HDR)])
@@ -346,6 +389,10 @@ def test_strong_scatterers_sliding_window(name):
     note(f"strong scatterers {name}: {H}x{W} {base} {prec}")
     Tg, Dg, xd = run_frame(plan, sc.x)
     ref, out = frame_oracle(sc.x, oracle_cfg(base))
+    T_tie, nties = regrade_stop_ties(kstap, plan, xd, Tg, ref, out, oracle_cfg(base), tol)
+    moved = T_tie != ref["T"]
+    ref["D"] = np.where(moved, (T_tie > plan.tau).astype(ref["D"].dtype), ref["D"])
+    ref["T"] = T_tie
     check_parity(Tg.ravel(), Dg.ravel(), ref, plan.tau, base["r_a"], base["r_b"], "hdr " + name, tol=tol)
     # pixels whose windows held a scatterer, and their neighbours in the chain
     st = plan.stencil
